@@ -1,0 +1,170 @@
+"""Pins of the CPU oracle to things other than itself: hand-worked examples,
+brute force over the definition, closed forms, an independent triple
+enumerator, invariants and metamorphic relations.  CPU only."""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import brute
+from paper_2507_14813_amd import workloads as W
+from conftest import edges_of, tiny_graph
+
+BIG = 10 ** 12
+
+
+def test_golden_examples(oracle_mod, golden_examples):
+    for ex in golden_examples:
+        s, d, t, n = edges_of(ex)
+        for c in ex["cases"]:
+            m = [tuple(e) for e in c["motif"]]
+            assert oracle_mod.count(s, d, t, n, m, c["delta"]) == c["count"], (ex["name"], c)
+            assert brute.count(s, d, t, m, c["delta"]) == c["count"], (ex["name"], c)
+
+
+def _tiny_motifs():
+    ms = []
+    for k in (1, 2, 3):
+        ms += W.enumerate_motifs(k, 2 * k, connected=False)
+    rng = np.random.default_rng(7)
+    four = W.enumerate_motifs(4, 5, connected=False)
+    ms += [four[i] for i in rng.choice(len(four), 25, replace=False)]
+    return ms
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_oracle_equals_brute_force(oracle_mod, seed):
+    rng = np.random.default_rng(100 + seed)
+    n_nodes = int(rng.integers(2, 7))
+    s, d, t = tiny_graph(rng, n_nodes, int(rng.integers(6, 11)), 10,
+                         self_loops=bool(seed % 2))
+    for m in _tiny_motifs():
+        for delta in (0, 1, 3, 5, BIG):
+            want = brute.count(s, d, t, m, delta)
+            got = oracle_mod.count(s, d, t, n_nodes, m, delta)
+            assert got == want, (m, delta)
+
+
+def test_single_edge_and_zero_window(oracle_mod):
+    rng = np.random.default_rng(3)
+    s, d, t = tiny_graph(rng, 30, 500, 200, self_loops=True)
+    assert oracle_mod.count(s, d, t, 30, [(0, 1)], 5) == int((s != d).sum())
+    for m in W.CONFIG1_MOTIFS + [((0, 1), (0, 1)), ((0, 1), (1, 0))]:
+        assert oracle_mod.count(s, d, t, 30, m, 0) == 0
+
+
+def _within(times_sorted, lo, hi):
+    """number of times in (lo, hi] per query"""
+    return (np.searchsorted(times_sorted, hi, side="right")
+            - np.searchsorted(times_sorted, lo, side="right"))
+
+
+@pytest.mark.parametrize("delta", [0, 3, 17, 1000])
+def test_closed_forms_two_edges(oracle_mod, delta):
+    rng = np.random.default_rng(11)
+    s, d, t = tiny_graph(rng, 12, 800, 400)
+    # repeated edge [(0,1),(0,1)]: per ordered pair, later times within delta
+    want_rep = 0
+    want_rec = 0
+    by_pair = {}
+    for a, b, x in zip(s.tolist(), d.tolist(), t.tolist()):
+        by_pair.setdefault((a, b), []).append(x)
+    by_pair = {k: np.sort(np.array(v)) for k, v in by_pair.items()}
+    for (a, b), ts in by_pair.items():
+        want_rep += int(_within(ts, ts, ts + delta).sum())
+        back = by_pair.get((b, a))
+        if back is not None:
+            want_rec += int(_within(back, ts, ts + delta).sum())
+    assert oracle_mod.count(s, d, t, 12, [(0, 1), (0, 1)], delta) == want_rep
+    assert oracle_mod.count(s, d, t, 12, [(0, 1), (1, 0)], delta) == want_rec
+
+
+@pytest.mark.parametrize("delta", [4, 25])
+def test_partition_identity_three_edges(oracle_mod, delta):
+    """The 36 three-edge motifs on <= 3 vertices partition all window triples
+    on <= 3 vertices (each triple has exactly one first-appearance form)."""
+    rng = np.random.default_rng(5)
+    s, d, t = tiny_graph(rng, 7, 70, 60)
+    o = np.lexsort((np.arange(len(t)), t))
+    s, d, t = s[o], d[o], t[o]
+    triples = 0
+    for i, j, k in itertools.combinations(range(len(t)), 3):
+        if not (t[i] < t[j] < t[k]) or t[k] - t[i] > delta:
+            continue
+        if len({s[i], d[i], s[j], d[j], s[k], d[k]}) <= 3:
+            triples += 1
+    got = sum(oracle_mod.count(s, d, t, 7, m, delta) for m in W.enumerate_motifs(3, 3))
+    assert got == triples and triples > 0
+
+
+def _medium():
+    rng = np.random.default_rng(21)
+    s, d, t = tiny_graph(rng, 15, 400, 300)
+    motifs = list(W.CONFIG1_MOTIFS) + W.random_extension_motifs(12, (2, 3, 4), 5, 9)
+    return s, d, t, 15, motifs, 20
+
+
+def test_metamorphic_relations(oracle_mod):
+    s, d, t, n, motifs, delta = _medium()
+    base = [oracle_mod.count(s, d, t, n, m, delta) for m in motifs]
+    assert sum(base) > 0
+    perm = np.random.default_rng(1).permutation(n).astype(np.int32)
+    rev = lambda m: [(v, u) for u, v in m]
+    for i, m in enumerate(motifs):
+        # relabel graph vertices
+        assert oracle_mod.count(perm[s], perm[d], t, n, m, delta) == base[i]
+        # shift time
+        assert oracle_mod.count(s, d, t + 12345, n, m, delta) == base[i]
+        # scale time and window together
+        assert oracle_mod.count(s, d, 7 * t, n, m, 7 * delta) == base[i]
+        # reverse time together with the motif's edge order
+        assert oracle_mod.count(s, d, 1000 - t, n, list(m)[::-1], delta) == base[i]
+        # reverse every edge of graph and motif
+        assert oracle_mod.count(d, s, t, n, rev(m), delta) == base[i]
+        # arbitrary motif labels
+        lab = {x: 10 * x + 3 for e in m for x in e}
+        assert oracle_mod.count(s, d, t, n, [(lab[u], lab[v]) for u, v in m],
+                                delta) == base[i]
+
+
+def test_window_monotone(oracle_mod):
+    s, d, t, n, motifs, _ = _medium()
+    for m in motifs:
+        c = [oracle_mod.count(s, d, t, n, m, dl) for dl in (0, 5, 20, 80, BIG)]
+        assert all(a <= b for a, b in zip(c, c[1:])), (m, c)
+
+
+def test_per_root_and_level_logs(oracle_mod):
+    s, d, t, n, motifs, delta = _medium()
+    s = s.copy()
+    s[::17] = d[::17]            # plant self-loops
+    o = np.lexsort((np.arange(len(t)), t))
+    for m in motifs:
+        tot, pr, lv = oracle_mod.count(s, d, t, n, m, delta, per_root=True, level=True)
+        assert int(pr.sum()) == tot
+        assert np.array_equal(lv[:, -1], pr)
+        assert np.array_equal(lv[:, 0], (s[o] != d[o]).astype(np.uint64))
+        roots = np.arange(3, len(t), 5)
+        assert oracle_mod.count(s, d, t, n, m, delta, roots=roots) == int(pr[roots].sum())
+        assert brute.count(s[:40], d[:40], t[:40], m, delta, roots=[0, 5, 9]) == \
+            oracle_mod.count(s[:40], d[:40], t[:40], n, m, delta, roots=[0, 5, 9])
+
+
+@pytest.mark.parametrize("mutant", [1, 2, 3, 4])
+def test_pins_catch_planted_mistakes(oracle_mod, golden_examples, mutant):
+    """Each planted mistake (non-strict order, no injectivity for new
+    vertices, exclusive window, window from the previous edge) is caught by
+    the golden examples or by brute force."""
+    caught = False
+    for ex in golden_examples:
+        s, d, t, n = edges_of(ex)
+        for c in ex["cases"]:
+            m = [tuple(e) for e in c["motif"]]
+            caught |= oracle_mod.count(s, d, t, n, m, c["delta"], mutant=mutant) != c["count"]
+    assert caught
+    rng = np.random.default_rng(100)
+    s, d, t = tiny_graph(rng, 5, 10, 10)
+    diff = 0
+    for m in _tiny_motifs()[:40]:
+        diff += oracle_mod.count(s, d, t, 5, m, 3, mutant=mutant) != brute.count(s, d, t, m, 3)
+    assert diff > 0
