@@ -20,6 +20,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 _lib = None
+_mutants = {}
 
 
 def build(force: bool = True, mutant: int = 0) -> str:
@@ -39,7 +40,9 @@ def build(force: bool = True, mutant: int = 0) -> str:
 def _load(mutant: int = 0):
     global _lib
     if mutant:
-        return _bind(ctypes.CDLL(build(force=False, mutant=mutant)))
+        if mutant not in _mutants:
+            _mutants[mutant] = _bind(ctypes.CDLL(build(force=True, mutant=mutant)))
+        return _mutants[mutant]
     if _lib is None:
         if not os.path.exists(_SO):
             build()
@@ -54,6 +57,13 @@ def _bind(lib):
                                  ctypes.c_int64, p, p, ctypes.c_int32, p]
     lib.oracle_count.restype = ctypes.c_int
     lib.oracle_max_threads.restype = ctypes.c_int
+    lib.oracle_graph_new.argtypes = [ctypes.c_int64, p, p, p, ctypes.c_int32]
+    lib.oracle_graph_new.restype = p
+    lib.oracle_graph_free.argtypes = [p]
+    lib.oracle_graph_free.restype = None
+    lib.oracle_graph_count.argtypes = [p, ctypes.c_int32, p, ctypes.c_int64, p,
+                                       ctypes.c_int64, p, p, p, ctypes.c_int32, p]
+    lib.oracle_graph_count.restype = ctypes.c_int
     return lib
 
 
@@ -99,3 +109,52 @@ def count_many(src, dst, t, n_nodes, motifs, delta, roots=None, threads=0):
     """Per-motif counts (list of ints), one oracle pass per motif."""
     return [count(src, dst, t, n_nodes, m, delta, roots=roots, threads=threads)
             for m in motifs]
+
+
+class OracleGraph:
+    """A graph loaded (sorted, adjacency built) once for many oracle counts."""
+
+    def __init__(self, src, dst, t, n_nodes):
+        src = np.ascontiguousarray(src, dtype=np.int32)
+        dst = np.ascontiguousarray(dst, dtype=np.int32)
+        t = np.ascontiguousarray(t, dtype=np.int64)
+        self._lib = _load()
+        self._h = self._lib.oracle_graph_new(len(src), _ptr(src), _ptr(dst), _ptr(t),
+                                             int(n_nodes))
+        if not self._h:
+            raise ValueError("oracle_graph_new failed (bad ids or out of memory)")
+        self.n_edges = len(src)
+
+    def count(self, motif, delta, roots=None, per_root=False, level=False,
+              windows=False, threads=0):
+        """Like ``count``; ``windows`` adds the per-edge window-entry totals."""
+        uv = np.ascontiguousarray(np.asarray(motif, dtype=np.int32).reshape(-1))
+        k = len(uv) // 2
+        r = None if roots is None else np.ascontiguousarray(roots, dtype=np.int64)
+        nr = self.n_edges if r is None else len(r)
+        pr = np.zeros(nr, dtype=np.uint64) if per_root else None
+        lv = np.zeros((nr, k), dtype=np.uint64) if level else None
+        wn = np.zeros(k, dtype=np.uint64) if windows else None
+        tot = np.zeros(1, dtype=np.uint64)
+        rc = self._lib.oracle_graph_count(self._h, k, _ptr(uv), int(delta), _ptr(r), nr,
+                                          _ptr(pr), _ptr(lv), _ptr(wn), int(threads),
+                                          _ptr(tot))
+        if rc != 0:
+            raise ValueError("oracle_graph_count failed with status %d" % rc)
+        if not (per_root or level or windows):
+            return int(tot[0])
+        out = [int(tot[0])]
+        if per_root:
+            out.append(pr)
+        if level:
+            out.append(lv)
+        if windows:
+            out.append(wn)
+        return tuple(out)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.oracle_graph_free(self._h)
+            self._h = None
+
+    __del__ = close

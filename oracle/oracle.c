@@ -76,6 +76,7 @@ typedef struct {
     int64_t t_first;
     uint64_t count;
     uint64_t *level;  /* k entries or NULL */
+    uint64_t *win;    /* k entries or NULL: window entries scanned per edge */
 } or_ctx;
 
 /* first position p in [lo,hi) of the edge-id list ids with t[ids[p]] > tv */
@@ -112,6 +113,7 @@ static void match_edge(or_ctx *c, int j, int64_t t_prev) {
         int64_t e = ids ? ids[p] : p;
         int64_t te = g->t[e];
         if (te > tmax || (ORACLE_MUTANT == 3 && te == tmax)) break;  /* window */
+        if (c->win) c->win[j]++;
         int32_t s = g->src[e], d = g->dst[e];
         /* structural filter */
         if (ug >= 0 && s != ug) continue;
@@ -131,9 +133,9 @@ static void match_edge(or_ctx *c, int j, int64_t t_prev) {
 
 /* one root: the root edge is the candidate for motif edge 1 */
 static uint64_t count_root(const or_graph *g, const or_motif *m, int64_t delta,
-                           int64_t r, uint64_t *level) {
+                           int64_t r, uint64_t *level, uint64_t *win) {
     or_ctx c;
-    c.g = g; c.m = m; c.delta = delta; c.count = 0; c.level = level;
+    c.g = g; c.m = m; c.delta = delta; c.count = 0; c.level = level; c.win = win;
     for (int i = 0; i < OR_MAX_V; i++) c.m2g[i] = -1;
     int32_t s = g->src[r], d = g->dst[r];
     if (s == d) return 0;                     /* injectivity */
@@ -212,49 +214,101 @@ static int load_motif(or_motif *m, int k, const int32_t *uv) {
     return 0;
 }
 
+typedef struct {
+    or_graph g;
+    int32_t *s2, *d2;
+    int64_t *t2;
+} oracle_graph;
+
 /*
- * Count one motif.
- *   src,dst,t : n_edges edges in any order (sorted here, stably, by t)
+ * Load a graph: src,dst,t are n_edges edges in any order; they are copied and
+ * stably sorted by t.  Returns NULL on a bad argument or when out of memory.
+ */
+oracle_graph *oracle_graph_new(int64_t n_edges, const int32_t *src, const int32_t *dst,
+                               const int64_t *t, int32_t n_nodes) {
+    if (n_edges < 0 || n_nodes < 0) return NULL;
+    for (int64_t i = 0; i < n_edges; i++)
+        if (src[i] < 0 || src[i] >= n_nodes || dst[i] < 0 || dst[i] >= n_nodes) return NULL;
+    oracle_graph *h = calloc(1, sizeof(oracle_graph));
+    if (!h) return NULL;
+    if (build(&h->g, n_edges, src, dst, t, n_nodes, &h->s2, &h->d2, &h->t2)) {
+        release(&h->g, h->s2, h->d2, h->t2);
+        free(h);
+        return NULL;
+    }
+    return h;
+}
+
+void oracle_graph_free(oracle_graph *h) {
+    if (!h) return;
+    release(&h->g, h->s2, h->d2, h->t2);
+    free(h);
+}
+
+/*
+ * Count one motif in a loaded graph.
  *   motif_uv  : 2k vertex labels, edge j = (motif_uv[2j], motif_uv[2j+1])
  *   roots     : positions in the stably time-sorted edge list to use as the
  *               first edge; NULL means every edge
  *   per_root  : NULL or n_roots counts (matches that start at each root)
  *   level     : NULL or n_roots*k: entry [r*k + j] = partial matches of the
  *               first j+1 motif edges that start at root r
+ *   win       : NULL or k totals: window entries scanned for motif edge j
+ *               (entry 0 stays 0: the first edge has no window)
  *   threads   : OpenMP threads (<=0: library default)
  *   total     : out, the count over the chosen roots
- * Returns 0, -1 on a bad argument, -2 when out of memory.
+ * Returns 0, -1 on a bad argument.
  */
+int oracle_graph_count(const oracle_graph *h, int32_t k, const int32_t *motif_uv,
+                       int64_t delta, const int64_t *roots, int64_t n_roots,
+                       uint64_t *per_root, uint64_t *level, uint64_t *win,
+                       int32_t threads, uint64_t *total) {
+    or_motif m;
+    if (!h || delta < 0 || !total) return -1;
+    if (load_motif(&m, k, motif_uv)) return -1;
+    const or_graph *g = &h->g;
+    if (!roots) n_roots = g->n;
+    for (int64_t r = 0; roots && r < n_roots; r++)
+        if (roots[r] < 0 || roots[r] >= g->n) return -1;
+    if (level) memset(level, 0, sizeof(uint64_t) * (size_t)n_roots * (size_t)k);
+    uint64_t sum = 0;
+    uint64_t wsum[OR_MAX_K] = {0};
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#endif
+    #pragma omp parallel
+    {
+        uint64_t wl[OR_MAX_K] = {0};
+        #pragma omp for schedule(dynamic, 64) reduction(+ : sum)
+        for (int64_t r = 0; r < n_roots; r++) {
+            int64_t e = roots ? roots[r] : r;
+            uint64_t c = count_root(g, &m, delta, e,
+                                    level ? level + (size_t)r * k : NULL, win ? wl : NULL);
+            if (per_root) per_root[r] = c;
+            sum += c;
+        }
+        if (win) {
+            #pragma omp critical
+            for (int j = 0; j < k; j++) wsum[j] += wl[j];
+        }
+    }
+    if (win) for (int j = 0; j < k; j++) win[j] = wsum[j];
+    *total = sum;
+    return 0;
+}
+
+/* One-shot form of oracle_graph_new + oracle_graph_count + oracle_graph_free. */
 int oracle_count(int64_t n_edges, const int32_t *src, const int32_t *dst,
                  const int64_t *t, int32_t n_nodes, int32_t k,
                  const int32_t *motif_uv, int64_t delta, const int64_t *roots,
                  int64_t n_roots, uint64_t *per_root, uint64_t *level,
                  int32_t threads, uint64_t *total) {
-    or_motif m;
-    if (n_edges < 0 || n_nodes < 0 || delta < 0 || !total) return -1;
-    if (load_motif(&m, k, motif_uv)) return -1;
-    for (int64_t i = 0; i < n_edges; i++)
-        if (src[i] < 0 || src[i] >= n_nodes || dst[i] < 0 || dst[i] >= n_nodes) return -1;
-    if (!roots) n_roots = n_edges;
-    for (int64_t r = 0; roots && r < n_roots; r++)
-        if (roots[r] < 0 || roots[r] >= n_edges) return -1;
-    or_graph g; int32_t *s2, *d2; int64_t *t2;
-    if (build(&g, n_edges, src, dst, t, n_nodes, &s2, &d2, &t2)) return -2;
-    if (level) memset(level, 0, sizeof(uint64_t) * (size_t)n_roots * (size_t)k);
-    uint64_t sum = 0;
-#ifdef _OPENMP
-    if (threads > 0) omp_set_num_threads(threads);
-#endif
-    #pragma omp parallel for schedule(dynamic, 64) reduction(+ : sum)
-    for (int64_t r = 0; r < n_roots; r++) {
-        int64_t e = roots ? roots[r] : r;
-        uint64_t c = count_root(&g, &m, delta, e, level ? level + (size_t)r * k : NULL);
-        if (per_root) per_root[r] = c;
-        sum += c;
-    }
-    *total = sum;
-    release(&g, s2, d2, t2);
-    return 0;
+    oracle_graph *h = oracle_graph_new(n_edges, src, dst, t, n_nodes);
+    if (!h) return -1;
+    int rc = oracle_graph_count(h, k, motif_uv, delta, roots, n_roots, per_root, level,
+                                NULL, threads, total);
+    oracle_graph_free(h);
+    return rc;
 }
 
 /* Threads an OpenMP parallel region would use. */

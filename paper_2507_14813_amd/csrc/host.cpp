@@ -1,0 +1,638 @@
+// Host side of the C ABI declared in include/mayura.h: graph ingest into
+// time-sorted adjacency, motif relabelling, MG-Tree / search-trie
+// construction and flattening, and the count dispatch.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/mayura.h"
+#include "comine.h"
+
+using mg::kVMax;
+using mg::kKMax;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                              \
+    do {                                                                           \
+        hipError_t e_ = (expr);                                                    \
+        if (e_ != hipSuccess)                                                      \
+            return fail(MG_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------- allocator
+mg_alloc_fn g_alloc = nullptr;
+mg_release_fn g_release = nullptr;
+void *g_alloc_ctx = nullptr;
+
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    void *stream = nullptr;
+    bool custom = false;
+    mg_release_fn release = nullptr;
+    void *ctx = nullptr;
+};
+
+int dev_alloc(DevBuf &b, size_t bytes, void *stream) {
+    b.bytes = bytes;
+    b.stream = stream;
+    if (bytes == 0) bytes = 16;
+    if (g_alloc) {
+        b.ptr = g_alloc(bytes, stream, g_alloc_ctx);
+        b.custom = true;
+        b.release = g_release;
+        b.ctx = g_alloc_ctx;
+        if (!b.ptr) return fail(MG_ENOMEM, "device allocator returned NULL for %zu bytes", bytes);
+        return MG_OK;
+    }
+    hipError_t e = hipMalloc(&b.ptr, bytes);
+    if (e != hipSuccess) {
+        b.ptr = nullptr;
+        return fail(MG_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    return MG_OK;
+}
+
+void dev_free(DevBuf &b) {
+    if (!b.ptr) return;
+    if (b.custom) {
+        if (b.release) b.release(b.ptr, b.stream, b.ctx);
+    } else {
+        (void)hipFree(b.ptr);
+    }
+    b.ptr = nullptr;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- graph
+struct mg_graph {
+    int64_t E = 0;
+    int32_t V = 0;
+    int64_t self_loops = 0;
+    int64_t t_min = 0, t_max = 0;
+    int time_bytes = 4;
+    int device = 0;
+    DevBuf gsrc, gdst, gt, out_off, out_nbr, out_t, in_off, in_nbr, in_t;
+    int64_t device_bytes = 0;
+    ~mg_graph() {
+        for (DevBuf *b : {&gsrc, &gdst, &gt, &out_off, &out_nbr, &out_t, &in_off, &in_nbr, &in_t})
+            dev_free(*b);
+    }
+};
+
+namespace {
+
+template <typename TT>
+int upload_graph(mg_graph *g, const std::vector<int32_t> &s, const std::vector<int32_t> &d,
+                 const std::vector<int64_t> &t, hipStream_t st) {
+    const int64_t E = g->E;
+    const int32_t V = g->V;
+    std::vector<TT> rt(E);
+    for (int64_t i = 0; i < E; ++i) rt[i] = (TT)(uint64_t)(t[i] - g->t_min);
+
+    // out/in adjacency (self-loops excluded), each list in time order:
+    // a counting sort by vertex over the time-ordered edge list is stable.
+    std::vector<uint32_t> oo(V + 1, 0), io(V + 1, 0);
+    for (int64_t i = 0; i < E; ++i)
+        if (s[i] != d[i]) { oo[s[i] + 1]++; io[d[i] + 1]++; }
+    for (int32_t v = 0; v < V; ++v) { oo[v + 1] += oo[v]; io[v + 1] += io[v]; }
+    const uint32_t A = oo[V];
+    std::vector<int32_t> on(A), in_(A);
+    std::vector<TT> ot(A), it(A);
+    {
+        std::vector<uint32_t> po(oo.begin(), oo.end() - 1), pi(io.begin(), io.end() - 1);
+        for (int64_t i = 0; i < E; ++i) {
+            if (s[i] == d[i]) continue;
+            uint32_t a = po[s[i]]++;
+            on[a] = d[i]; ot[a] = rt[i];
+            uint32_t b = pi[d[i]]++;
+            in_[b] = s[i]; it[b] = rt[i];
+        }
+    }
+    struct Up { DevBuf *b; const void *h; size_t n; };
+    Up ups[] = {
+        {&g->gsrc, s.data(), sizeof(int32_t) * E}, {&g->gdst, d.data(), sizeof(int32_t) * E},
+        {&g->gt, rt.data(), sizeof(TT) * E},
+        {&g->out_off, oo.data(), sizeof(uint32_t) * (V + 1)},
+        {&g->out_nbr, on.data(), sizeof(int32_t) * A}, {&g->out_t, ot.data(), sizeof(TT) * A},
+        {&g->in_off, io.data(), sizeof(uint32_t) * (V + 1)},
+        {&g->in_nbr, in_.data(), sizeof(int32_t) * A}, {&g->in_t, it.data(), sizeof(TT) * A},
+    };
+    g->device_bytes = 0;
+    for (auto &u : ups) {
+        int rc = dev_alloc(*u.b, u.n, (void *)st);
+        if (rc) return rc;
+        if (u.n) HIP_TRY(hipMemcpyAsync(u.b->ptr, u.h, u.n, hipMemcpyHostToDevice, st));
+        g->device_bytes += (int64_t)u.n;
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    return MG_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- tree
+namespace {
+
+struct TrieNode {
+    int parent = -1;
+    int u = 0, v = 0;      // edge that extends the parent (canonical labels)
+    int depth = 0;         // edges in the prefix
+    int nv = 0;            // vertices bound after the prefix
+    std::vector<int> kids;
+    int q = -1;            // distinct motif whose edge sequence is this prefix
+};
+
+using Motif = std::vector<std::pair<int, int>>;
+
+}  // namespace
+
+struct mg_tree {
+    int32_t n_motifs = 0;
+    int64_t delta = 0;
+    std::vector<int32_t> motif_q;       // caller motif -> distinct id
+    std::vector<Motif> distinct;
+    std::vector<TrieNode> nodes;        // node 0 = prefix ((0,1))
+    std::vector<int32_t> node_tab;      // 4 ints per node
+    std::vector<int32_t> grp_tab;       // 8 ints per group
+    int32_t depth = 0, root_q = -1;
+    mg_tree_info_t info{};
+    // device copies
+    int device = -1;
+    DevBuf d_node, d_grp;
+    // per-motif chain trees (built on first per-motif count)
+    std::vector<std::unique_ptr<mg_tree>> singles;
+    ~mg_tree() { dev_free(d_node); dev_free(d_grp); }
+};
+
+namespace {
+
+// First-appearance relabelling: vertices are numbered in the order they are
+// first seen, source before destination.  Two motifs are the same ordered
+// edge sequence up to relabelling iff their relabelled forms are equal.
+int canonical(const int32_t *uv, int k, Motif &out) {
+    std::vector<std::pair<int32_t, int>> seen;
+    auto id = [&](int32_t x) {
+        for (auto &p : seen) if (p.first == x) return p.second;
+        seen.push_back({x, (int)seen.size()});
+        return (int)seen.size() - 1;
+    };
+    out.clear();
+    for (int j = 0; j < k; ++j) {
+        int32_t a = uv[2 * j], b = uv[2 * j + 1];
+        if (a < 0 || b < 0) return fail(MG_EINVAL, "motif vertex label < 0");
+        if (a == b) return fail(MG_EINVAL, "motif edge %d is a self-loop", j);
+        int ia = id(a), ib = id(b);
+        out.push_back({ia, ib});
+    }
+    if ((int)seen.size() > kVMax)
+        return fail(MG_EUNSUPPORTED, "motif has %d vertices (limit %d)", (int)seen.size(), kVMax);
+    return MG_OK;
+}
+
+// Build the prefix trie, then the flat tables the kernel reads.
+int build_tree(mg_tree *tr) {
+    tr->nodes.clear();
+    TrieNode root;
+    root.u = 0; root.v = 1; root.depth = 1; root.nv = 2;
+    tr->nodes.push_back(root);
+    for (size_t q = 0; q < tr->distinct.size(); ++q) {
+        const Motif &m = tr->distinct[q];
+        int cur = 0;
+        for (size_t j = 1; j < m.size(); ++j) {
+            int found = -1;
+            for (int c : tr->nodes[cur].kids)
+                if (tr->nodes[c].u == m[j].first && tr->nodes[c].v == m[j].second) found = c;
+            if (found < 0) {
+                TrieNode n;
+                n.parent = cur;
+                n.u = m[j].first; n.v = m[j].second;
+                n.depth = tr->nodes[cur].depth + 1;
+                int hi = std::max(n.u, n.v);
+                n.nv = std::max(tr->nodes[cur].nv, hi + 1);
+                found = (int)tr->nodes.size();
+                tr->nodes.push_back(n);
+                tr->nodes[cur].kids.push_back(found);
+            }
+            cur = found;
+        }
+        tr->nodes[cur].q = (int)q;
+    }
+    // flat tables: BFS order is creation order already (parents first)
+    const int N = (int)tr->nodes.size();
+    tr->node_tab.assign(4 * N, 0);
+    tr->grp_tab.clear();
+    tr->depth = 0;
+    for (int n = 0; n < N; ++n) {
+        const TrieNode &nd = tr->nodes[n];
+        tr->depth = std::max(tr->depth, nd.depth);
+        // group the children by the list they scan
+        std::map<std::pair<int, int>, std::vector<int>> groups;
+        for (int c : nd.kids) {
+            const TrieNode &ch = tr->nodes[c];
+            int dir, anc;
+            if (ch.u < nd.nv) { dir = mg::kDirOut; anc = ch.u; }
+            else if (ch.v < nd.nv) { dir = mg::kDirIn; anc = ch.v; }
+            else { dir = mg::kDirAll; anc = 0; }
+            groups[{dir, anc}].push_back(c);
+        }
+        const int g0 = (int)tr->grp_tab.size() / 8;
+        for (auto &kv : groups) {
+            int32_t rec[8] = {kv.first.first | (kv.first.second << 4), -1, -1, -1, -1, -1, -1, -1};
+            for (int c : kv.second) {
+                const TrieNode &ch = tr->nodes[c];
+                if (kv.first.first == mg::kDirOut && ch.v < nd.nv) rec[2 + ch.v] = c;
+                else rec[1] = c;   // edge to a new vertex (or two new vertices)
+            }
+            tr->grp_tab.insert(tr->grp_tab.end(), rec, rec + 8);
+        }
+        tr->node_tab[4 * n + 0] = nd.q;
+        tr->node_tab[4 * n + 1] = g0;
+        tr->node_tab[4 * n + 2] = (int)groups.size();
+        tr->node_tab[4 * n + 3] = nd.nv | ((nd.kids.empty() ? 0 : 1) << 8);
+    }
+    if (tr->grp_tab.empty()) tr->grp_tab.assign(8, -1);
+    tr->root_q = tr->nodes[0].q;
+
+    // MG-Tree view: the root is the longest prefix shared by every motif;
+    // below it a node exists where a prefix is a query or branches.
+    int r = 0;
+    while (tr->nodes[r].q < 0 && tr->nodes[r].kids.size() == 1) r = tr->nodes[r].kids[0];
+    int mg_nodes = 0;
+    std::vector<int> stack{r};
+    while (!stack.empty()) {
+        int n = stack.back();
+        stack.pop_back();
+        const TrieNode &nd = tr->nodes[n];
+        if (n == r || nd.q >= 0 || nd.kids.size() != 1) mg_nodes++;
+        for (int c : nd.kids) stack.push_back(c);
+    }
+    long total_edges = 0;
+    for (auto &m : tr->distinct) total_edges += (long)m.size();
+    mg_tree_info_t &in = tr->info;
+    in.n_motifs = tr->n_motifs;
+    in.n_distinct = (int32_t)tr->distinct.size();
+    in.n_prefixes = N;
+    in.n_nodes = mg_nodes;
+    in.depth = tr->depth;
+    in.root_edges = tr->nodes[r].depth;
+    in.similarity = total_edges ? 1.0 - (double)N / (double)total_edges : 0.0;
+    in.delta = tr->delta;
+    return MG_OK;
+}
+
+int make_tree(const std::vector<Motif> &canon, int64_t delta, mg_tree **out) {
+    std::unique_ptr<mg_tree> tr(new (std::nothrow) mg_tree);
+    if (!tr) return fail(MG_ENOMEM, "out of host memory");
+    tr->n_motifs = (int32_t)canon.size();
+    tr->delta = delta;
+    std::map<Motif, int> ids;
+    for (const Motif &m : canon) {
+        auto it = ids.find(m);
+        int q;
+        if (it == ids.end()) {
+            q = (int)tr->distinct.size();
+            ids[m] = q;
+            tr->distinct.push_back(m);
+        } else {
+            q = it->second;
+        }
+        tr->motif_q.push_back(q);
+    }
+    if ((int)tr->distinct.size() > MG_MAX_QUERIES)
+        return fail(MG_EUNSUPPORTED, "%d distinct motifs (limit %d)", (int)tr->distinct.size(),
+                    MG_MAX_QUERIES);
+    int rc = build_tree(tr.get());
+    if (rc) return rc;
+    *out = tr.release();
+    return MG_OK;
+}
+
+int upload_tree(mg_tree *tr, int device, hipStream_t st) {
+    if (tr->device == device && tr->d_node.ptr) return MG_OK;
+    dev_free(tr->d_node);
+    dev_free(tr->d_grp);
+    int rc = dev_alloc(tr->d_node, tr->node_tab.size() * 4, (void *)st);
+    if (rc) return rc;
+    rc = dev_alloc(tr->d_grp, tr->grp_tab.size() * 4, (void *)st);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(tr->d_node.ptr, tr->node_tab.data(), tr->node_tab.size() * 4,
+                           hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(tr->d_grp.ptr, tr->grp_tab.data(), tr->grp_tab.size() * 4,
+                           hipMemcpyHostToDevice, st));
+    tr->device = device;
+    return MG_OK;
+}
+
+// One launch of the co-mining kernel over a tree; counts land in d_counts.
+template <typename TT>
+int launch_tree(const mg_graph *g, mg_tree *tr, const uint32_t *d_roots, uint32_t n_roots,
+                uint32_t *d_cursor, unsigned long long *d_counts, unsigned long long *d_stats,
+                const mg_count_opts &o, hipStream_t st, float *ms) {
+    mg::KParams<TT> p{};
+    p.g.gsrc = (const int32_t *)g->gsrc.ptr;
+    p.g.gdst = (const int32_t *)g->gdst.ptr;
+    p.g.gt = (const TT *)g->gt.ptr;
+    p.g.out_off = (const uint32_t *)g->out_off.ptr;
+    p.g.out_nbr = (const int32_t *)g->out_nbr.ptr;
+    p.g.out_t = (const TT *)g->out_t.ptr;
+    p.g.in_off = (const uint32_t *)g->in_off.ptr;
+    p.g.in_nbr = (const int32_t *)g->in_nbr.ptr;
+    p.g.in_t = (const TT *)g->in_t.ptr;
+    p.g.n_edges = (uint32_t)g->E;
+    p.tree.node = (const int4 *)tr->d_node.ptr;
+    p.tree.grp = (const int4 *)tr->d_grp.ptr;
+    p.tree.n_q = (int32_t)tr->distinct.size();
+    p.tree.root_q = tr->root_q;
+    p.tree.depth = tr->depth;
+    if (sizeof(TT) == 4)
+        p.delta_sat = (TT)std::min<uint64_t>((uint64_t)tr->delta, 0xffffffffull);
+    else
+        p.delta_sat = (TT)(uint64_t)tr->delta;
+    p.roots = d_roots;
+    p.n_roots = n_roots;
+    p.chunk = (uint32_t)(o.chunk > 0 ? o.chunk : 256);
+    p.cursor = d_cursor;
+    p.counts = d_counts;
+    p.stats = d_stats;
+
+    HIP_TRY(hipMemsetAsync(d_cursor, 0, sizeof(uint32_t), st));
+    if (d_stats) HIP_TRY(hipMemsetAsync(d_stats, 0, sizeof(unsigned long long) * mg::kStats, st));
+    HIP_TRY(hipMemsetAsync(d_counts, 0, sizeof(unsigned long long) * p.tree.n_q, st));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ms) {
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        HIP_TRY(hipEventRecord(e0, st));
+    }
+    if (n_roots > 0) {
+        hipError_t e = mg::launch_comine<TT>(p, o.blocks, st);
+        if (e != hipSuccess)
+            return fail(MG_EDEVICE, "co-mining launch failed: %s", hipGetErrorString(e));
+    }
+    if (ms) {
+        HIP_TRY(hipEventRecord(e1, st));
+        HIP_TRY(hipEventSynchronize(e1));
+        HIP_TRY(hipEventElapsedTime(ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    return MG_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- C ABI
+extern "C" {
+
+int mg_set_allocator(mg_alloc_fn alloc, mg_release_fn release, void *ctx) {
+    if ((alloc == nullptr) != (release == nullptr))
+        return fail(MG_EINVAL, "alloc and release must both be set or both be NULL");
+    g_alloc = alloc;
+    g_release = release;
+    g_alloc_ctx = ctx;
+    return MG_OK;
+}
+
+const char *mg_last_error(void) { return g_err.c_str(); }
+
+int mg_graph_create(const int32_t *src, const int32_t *dst, const int64_t *t, int64_t n_edges,
+                    int32_t n_nodes, uint32_t flags, void *stream, mg_graph **out) {
+    try {
+        if (!out) return fail(MG_EINVAL, "out is NULL");
+        if (n_edges < 0 || n_nodes < 0) return fail(MG_EINVAL, "negative size");
+        if (n_edges > 0 && (!src || !dst || !t)) return fail(MG_EINVAL, "NULL edge array");
+        if (n_edges >= (int64_t)1 << 31)
+            return fail(MG_EUNSUPPORTED, "n_edges %lld >= 2^31", (long long)n_edges);
+        if (n_nodes >= INT32_MAX) return fail(MG_EUNSUPPORTED, "n_nodes too large");
+        for (int64_t i = 0; i < n_edges; ++i)
+            if (src[i] < 0 || src[i] >= n_nodes || dst[i] < 0 || dst[i] >= n_nodes)
+                return fail(MG_EINVAL, "edge %lld has a vertex outside [0, %d)", (long long)i,
+                            n_nodes);
+        bool sorted = true;
+        for (int64_t i = 1; i < n_edges; ++i)
+            if (t[i] < t[i - 1]) { sorted = false; break; }
+        if ((flags & MG_SORTED_BY_T) && !sorted)
+            return fail(MG_EINVAL, "MG_SORTED_BY_T given but t is not non-decreasing");
+        std::unique_ptr<mg_graph> g(new (std::nothrow) mg_graph);
+        if (!g) return fail(MG_ENOMEM, "out of host memory");
+        g->E = n_edges;
+        g->V = n_nodes;
+        std::vector<int32_t> s(n_edges), d(n_edges);
+        std::vector<int64_t> tt(n_edges);
+        if (sorted) {
+            std::copy(src, src + n_edges, s.begin());
+            std::copy(dst, dst + n_edges, d.begin());
+            std::copy(t, t + n_edges, tt.begin());
+        } else {
+            std::vector<int64_t> ord(n_edges);
+            std::iota(ord.begin(), ord.end(), 0);
+            std::stable_sort(ord.begin(), ord.end(),
+                             [&](int64_t a, int64_t b) { return t[a] < t[b]; });
+            for (int64_t i = 0; i < n_edges; ++i) {
+                s[i] = src[ord[i]]; d[i] = dst[ord[i]]; tt[i] = t[ord[i]];
+            }
+        }
+        for (int64_t i = 0; i < n_edges; ++i) g->self_loops += (s[i] == d[i]);
+        g->t_min = n_edges ? tt[0] : 0;
+        g->t_max = n_edges ? tt[n_edges - 1] : 0;
+        if (n_edges && g->t_max - g->t_min < 0) return fail(MG_EUNSUPPORTED, "time span >= 2^63");
+        const uint64_t span = n_edges ? (uint64_t)(g->t_max - g->t_min) : 0;
+        g->time_bytes = span < 0xffffffffull ? 4 : 8;
+        HIP_TRY(hipGetDevice(&g->device));
+        hipStream_t st = (hipStream_t)stream;
+        int rc = g->time_bytes == 4 ? upload_graph<uint32_t>(g.get(), s, d, tt, st)
+                                    : upload_graph<uint64_t>(g.get(), s, d, tt, st);
+        if (rc) return rc;
+        *out = g.release();
+        return MG_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(MG_ENOMEM, "out of host memory");
+    } catch (...) {
+        return fail(MG_EINTERNAL, "unexpected exception");
+    }
+}
+
+int mg_graph_info(const mg_graph *g, mg_graph_info_t *out) {
+    if (!g || !out) return fail(MG_EINVAL, "NULL argument");
+    out->n_edges = g->E;
+    out->n_nodes = g->V;
+    out->self_loops = g->self_loops;
+    out->t_min = g->t_min;
+    out->t_max = g->t_max;
+    out->time_bytes = g->time_bytes;
+    out->device_bytes = g->device_bytes;
+    return MG_OK;
+}
+
+void mg_graph_destroy(mg_graph *g) { delete g; }
+
+int mg_tree_create(const int32_t *motif_uv, const int32_t *motif_k, int32_t n_motifs,
+                   int64_t delta, mg_tree **out) {
+    try {
+        if (!out) return fail(MG_EINVAL, "out is NULL");
+        if (n_motifs < 1 || !motif_uv || !motif_k) return fail(MG_EINVAL, "no motifs");
+        if (delta < 0) return fail(MG_EINVAL, "delta < 0");
+        std::vector<Motif> canon(n_motifs);
+        int64_t off = 0;
+        for (int32_t i = 0; i < n_motifs; ++i) {
+            const int k = motif_k[i];
+            if (k < 1) return fail(MG_EINVAL, "motif %d has %d edges", i, k);
+            if (k > kKMax)
+                return fail(MG_EUNSUPPORTED, "motif %d has %d edges (limit %d)", i, k, kKMax);
+            int rc = canonical(motif_uv + 2 * off, k, canon[i]);
+            if (rc) return rc;
+            off += k;
+        }
+        return make_tree(canon, delta, out);
+    } catch (const std::bad_alloc &) {
+        return fail(MG_ENOMEM, "out of host memory");
+    } catch (...) {
+        return fail(MG_EINTERNAL, "unexpected exception");
+    }
+}
+
+int mg_tree_info(const mg_tree *tr, mg_tree_info_t *out) {
+    if (!tr || !out) return fail(MG_EINVAL, "NULL argument");
+    *out = tr->info;
+    return MG_OK;
+}
+
+void mg_tree_destroy(mg_tree *tr) { delete tr; }
+
+void mg_count_opts_init(mg_count_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->mode = MG_MODE_COMINE;
+}
+
+int mg_count(const mg_graph *g, const mg_tree *tr_c, const mg_count_opts *opts,
+             uint64_t *counts) {
+    try {
+        if (!g || !tr_c || !counts) return fail(MG_EINVAL, "NULL argument");
+        mg_tree *tr = const_cast<mg_tree *>(tr_c);   // device copy is a cache
+        mg_count_opts o;
+        mg_count_opts_init(&o);
+        if (opts) o = *opts;
+        if (o.mode != MG_MODE_COMINE && o.mode != MG_MODE_PER_MOTIF)
+            return fail(MG_EINVAL, "unknown mode %d", o.mode);
+        if (o.chunk < 0 || (o.chunk % 64) != 0 || o.chunk > (1 << 20))
+            return fail(MG_EINVAL, "chunk must be a multiple of 64 in [0, 2^20]");
+        if (o.roots && o.n_roots < 0) return fail(MG_EINVAL, "n_roots < 0");
+        int dev = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        if (dev != g->device) return fail(MG_EINVAL, "graph lives on device %d, current is %d",
+                                          g->device, dev);
+        hipStream_t st = (hipStream_t)o.stream;
+
+        // roots
+        DevBuf d_roots;
+        uint32_t n_roots = (uint32_t)g->E;
+        if (o.roots) {
+            std::vector<uint32_t> r(o.n_roots);
+            for (int64_t i = 0; i < o.n_roots; ++i) {
+                if (o.roots[i] < 0 || o.roots[i] >= g->E)
+                    return fail(MG_EINVAL, "root %lld outside [0, %lld)", (long long)o.roots[i],
+                                (long long)g->E);
+                r[i] = (uint32_t)o.roots[i];
+            }
+            n_roots = (uint32_t)o.n_roots;
+            int rc = dev_alloc(d_roots, sizeof(uint32_t) * r.size(), (void *)st);
+            if (rc) return rc;
+            if (!r.empty())
+                HIP_TRY(hipMemcpyAsync(d_roots.ptr, r.data(), sizeof(uint32_t) * r.size(),
+                                       hipMemcpyHostToDevice, st));
+        }
+        struct Guard { DevBuf *b; ~Guard() { dev_free(*b); } } gr{&d_roots};
+
+        // trees to run: the whole group, or one chain per distinct motif
+        std::vector<mg_tree *> runs;
+        if (o.mode == MG_MODE_COMINE) {
+            runs.push_back(tr);
+        } else {
+            if (tr->singles.empty()) {
+                for (const Motif &m : tr->distinct) {
+                    mg_tree *one = nullptr;
+                    int rc = make_tree({m}, tr->delta, &one);
+                    if (rc) return rc;
+                    tr->singles.emplace_back(one);
+                }
+            }
+            for (auto &u : tr->singles) runs.push_back(u.get());
+        }
+        size_t maxq = 1;
+        for (mg_tree *t : runs) maxq = std::max(maxq, t->distinct.size());
+        static_assert(mg::kStats == MG_NSTATS, "stats layout");
+        DevBuf d_work;
+        const size_t stats_off = 16 + 8 * maxq;
+        int rc = dev_alloc(d_work, stats_off + 8 * mg::kStats, (void *)st);
+        if (rc) return rc;
+        struct Guard2 { DevBuf *b; ~Guard2() { dev_free(*b); } } gw{&d_work};
+        uint32_t *d_cursor = (uint32_t *)d_work.ptr;
+        unsigned long long *d_counts = (unsigned long long *)((char *)d_work.ptr + 16);
+        unsigned long long *d_stats =
+            o.stats ? (unsigned long long *)((char *)d_work.ptr + stats_off) : nullptr;
+        std::vector<uint64_t> stats_sum(mg::kStats, 0);
+
+        std::vector<uint64_t> qcount(tr->distinct.size(), 0);
+        float total_ms = 0.f;
+        for (size_t ri = 0; ri < runs.size(); ++ri) {
+            mg_tree *t = runs[ri];
+            rc = upload_tree(t, dev, st);
+            if (rc) return rc;
+            float ms = 0.f;
+            rc = g->time_bytes == 4
+                     ? launch_tree<uint32_t>(g, t, (const uint32_t *)d_roots.ptr, n_roots,
+                                             d_cursor, d_counts, d_stats, o, st,
+                                             o.elapsed_ms ? &ms : nullptr)
+                     : launch_tree<uint64_t>(g, t, (const uint32_t *)d_roots.ptr, n_roots,
+                                             d_cursor, d_counts, d_stats, o, st,
+                                             o.elapsed_ms ? &ms : nullptr);
+            if (rc) return rc;
+            total_ms += ms;
+            std::vector<uint64_t> h(t->distinct.size());
+            HIP_TRY(hipMemcpyAsync(h.data(), d_counts, 8 * h.size(), hipMemcpyDeviceToHost, st));
+            std::vector<uint64_t> hs(mg::kStats, 0);
+            if (d_stats)
+                HIP_TRY(hipMemcpyAsync(hs.data(), d_stats, 8 * hs.size(), hipMemcpyDeviceToHost,
+                                       st));
+            HIP_TRY(hipStreamSynchronize(st));
+            for (int i = 0; i < mg::kStats; ++i) stats_sum[i] += hs[i];
+            if (o.mode == MG_MODE_COMINE) qcount = h;
+            else qcount[ri] = h[0];
+        }
+        for (int32_t i = 0; i < tr->n_motifs; ++i) counts[i] = qcount[tr->motif_q[i]];
+        if (o.elapsed_ms) *o.elapsed_ms = total_ms;
+        if (o.stats) std::copy(stats_sum.begin(), stats_sum.end(), o.stats);
+        return MG_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(MG_ENOMEM, "out of host memory");
+    } catch (...) {
+        return fail(MG_EINTERNAL, "unexpected exception");
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,278 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle: bit-exact
+uint64 counts on tiny, medium and configuration-shaped graphs, sampled roots
+of the full-size benchmark graph, schedule independence, search statistics
+and edge cases."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2507_14813_amd import api, workloads as W
+from oracle import OracleGraph
+from conftest import edges_of, tiny_graph
+
+pytestmark = pytest.mark.gpu
+BIG = 10 ** 12
+
+
+def say(*a):
+    print("[gpu-case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "no GPU visible"
+    api.lib()
+    return torch
+
+
+def gpu_count(s, d, t, n, motifs, delta, **kw):
+    say("count", "E=%d" % len(s), "V=%d" % n, "motifs=%d" % len(motifs), "delta=%d" % delta, kw)
+    g = api.Graph(s, d, t, n)
+    tr = api.Tree(motifs, delta)
+    return api.count(g, tr, **kw)
+
+
+def oracle_counts(og, motifs, delta, roots=None):
+    return np.array([og.count(m, delta, roots=roots) for m in motifs], dtype=np.uint64)
+
+
+def test_golden_examples(golden_examples, oracle_mod):
+    for ex in golden_examples:
+        s, d, t, n = edges_of(ex)
+        by_delta = {}
+        for c in ex["cases"]:
+            by_delta.setdefault(c["delta"], []).append(c)
+        for delta, cases in by_delta.items():
+            motifs = [[tuple(e) for e in c["motif"]] for c in cases]
+            want = [c["count"] for c in cases]
+            for mode in ("comine", "per_motif"):
+                got = gpu_count(s, d, t, n, motifs, delta, mode=mode)
+                assert got.tolist() == want, (ex["name"], delta, mode)
+
+
+def _tiny_motifs():
+    ms = []
+    for k in (1, 2, 3):
+        ms += W.enumerate_motifs(k, 2 * k, connected=False)
+    rng = np.random.default_rng(7)
+    four = W.enumerate_motifs(4, 5, connected=False)
+    ms += [four[i] for i in rng.choice(len(four), 40, replace=False)]
+    five = W.enumerate_motifs(5, 6, connected=False)
+    ms += [five[i] for i in rng.choice(len(five), 40, replace=False)]
+    return ms
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_tiny_random_graphs(seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(2, 8))
+    s, d, t = tiny_graph(rng, n, int(rng.integers(6, 15)), 10, self_loops=bool(seed % 2))
+    og = OracleGraph(s, d, t, n)
+    ms = _tiny_motifs()
+    for delta in (0, 1, 3, 5, BIG):
+        want = oracle_counts(og, ms, delta)
+        got = gpu_count(s, d, t, n, ms, delta)
+        assert np.array_equal(got, want), delta
+
+
+def _medium(seed=1, E=4000, V=40, tmax=600):
+    rng = np.random.default_rng(seed)
+    s, d, t = tiny_graph(rng, V, E, tmax, self_loops=True)
+    ms = (W.random_extension_motifs(30, (2, 3, 4, 5), 6, seed)
+          + [m for m in W.enumerate_motifs(3, 6, connected=False) if max(max(e) for e in m) >= 3][:20])
+    return s, d, t, V, ms
+
+
+@pytest.mark.parametrize("delta", [7, 40])
+def test_medium_graph_all_modes(delta):
+    s, d, t, n, ms = _medium()
+    og = OracleGraph(s, d, t, n)
+    want = oracle_counts(og, ms, delta)
+    assert want.sum() > 0
+    g = api.Graph(s, d, t, n)
+    tr = api.Tree(ms, delta)
+    say("medium", delta)
+    assert np.array_equal(api.count(g, tr), want)
+    assert np.array_equal(api.count(g, tr, mode="per_motif"), want)
+    for blocks, chunk in ((1, 64), (3, 128), (0, 1024), (0, 64)):
+        say("schedule", blocks, chunk)
+        assert np.array_equal(api.count(g, tr, blocks=blocks, chunk=chunk), want)
+    roots = np.arange(5, len(s), 7)
+    say("roots subset")
+    assert np.array_equal(api.count(g, tr, roots=roots), oracle_counts(og, ms, delta, roots))
+
+
+def _trie_expectations(og, motifs, delta):
+    """Search statistics the co-mining search must produce, derived from the
+    oracle's per-motif counts and window logs: each distinct prefix is matched
+    once, each (prefix, list) pair opens one window per match of the prefix."""
+    def canon(m):
+        lab = {}
+        out = []
+        for u, v in m:
+            for x in (u, v):
+                if x not in lab:
+                    lab[x] = len(lab)
+            out.append((lab[u], lab[v]))
+        return tuple(out)
+
+    prefixes = set()
+    for m in motifs:
+        c = canon(m)
+        for j in range(1, len(c) + 1):
+            prefixes.add(c[:j])
+    kids = {}
+    for p in prefixes:
+        if len(p) > 1:
+            kids.setdefault(p[:-1], []).append(p)
+    cnt = {p: og.count(list(p), delta) for p in prefixes}
+    st = dict(win_list=0, win_all=0, ent_list=0, ent_all=0, push=0, credit=0)
+    for p in prefixes:
+        if len(p) > 1:
+            st["credit"] += cnt[p]
+            if p in kids:
+                st["push"] += cnt[p]
+        if p not in kids:
+            continue
+        nv = 1 + max(max(e) for e in p)
+        groups = {}
+        for c in kids[p]:
+            u, v = c[-1]
+            key = ("out", u) if u < nv else (("in", v) if v < nv else ("all", 0))
+            groups.setdefault(key, c)
+        for key, c in groups.items():
+            _, wins = og.count(list(c), delta, windows=True)
+            name = "all" if key[0] == "all" else "list"
+            st["win_" + name] += cnt[p]
+            st["ent_" + name] += int(wins[len(p)])
+    return st
+
+
+def test_search_statistics_match_oracle():
+    s, d, t, n, ms = _medium(seed=3, E=2500)
+    og = OracleGraph(s, d, t, n)
+    want = _trie_expectations(og, ms, 30)
+    g = api.Graph(s, d, t, n)
+    tr = api.Tree(ms, 30)
+    say("stats")
+    counts, st = api.count(g, tr, stats=True)
+    assert np.array_equal(counts, oracle_counts(og, ms, 30))
+    assert st["roots"] == int((s != d).sum())
+    for k, v in want.items():
+        assert st[k] == v, (k, st[k], v)
+
+
+def test_config1_full():
+    wl = W.make_config(1)
+    s, d, t, n = wl.graphs[0]
+    og = OracleGraph(s, d, t, n)
+    ms, delta = wl.motif_sets[0], wl.deltas[0]
+    want = oracle_counts(og, ms, delta)
+    assert np.array_equal(gpu_count(s, d, t, n, ms, delta), want)
+    assert np.array_equal(gpu_count(s, d, t, n, ms, delta, mode="per_motif"), want)
+
+
+@pytest.mark.parametrize("k,scale", [(2, 0.01), (4, 0.002), (5, 0.0005)])
+def test_config_minis(k, scale):
+    wl = W.make_config(k, scale=scale)
+    s, d, t, n = wl.graphs[0]
+    og = OracleGraph(s, d, t, n)
+    ms = wl.motif_sets[0]
+    g = api.Graph(s, d, t, n)
+    for delta in wl.deltas:
+        want = oracle_counts(og, ms, delta)
+        tr = api.Tree(ms, delta)
+        say("config", k, scale, delta)
+        assert np.array_equal(api.count(g, tr), want), (k, delta)
+
+
+def test_config2_full_size_sampled_roots():
+    """The benchmark's graph at full size (20M edges), launched exactly as the
+    benchmark launches it, checked on sampled roots the oracle can afford."""
+    wl = W.make_config(2)
+    s, d, t, n = wl.graphs[0]
+    ms, delta = wl.motif_sets[0], wl.deltas[0]
+    E = len(s)
+    rng = np.random.default_rng(0)
+    roots = np.concatenate([np.arange(q, q + 8192) for q in (0, E // 3, (2 * E) // 3, E - 8192)]
+                           + [np.sort(rng.choice(E, 16384, replace=False))])
+    og = OracleGraph(s, d, t, n)
+    want = oracle_counts(og, ms, delta, roots)
+    assert want.sum() > 0
+    g = api.Graph(s, d, t, n)
+    tr = api.Tree(ms, delta)
+    say("config2 full sampled")
+    assert np.array_equal(api.count(g, tr, roots=roots), want)
+    say("config2 full: co-mine vs per-motif on every root")
+    full = api.count(g, tr)
+    assert np.array_equal(api.count(g, tr, mode="per_motif"), full)
+    # single-edge count of the whole graph is the number of non-self-loop edges
+    one = api.count(g, api.Tree([[(0, 1)]], delta))
+    assert int(one[0]) == int((s != d).sum())
+
+
+def test_edge_cases(oracle_mod):
+    ms = [[(0, 1)], [(0, 1), (1, 2)], [(0, 1), (2, 3), (1, 2)]]
+    # empty graph
+    say("empty graph")
+    assert gpu_count(np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int64), 3,
+                     ms, 5).tolist() == [0, 0, 0]
+    # only self-loops
+    say("self-loops only")
+    z = np.array([0, 1, 1], np.int32)
+    assert gpu_count(z, z, np.array([1, 2, 3]), 2, ms, 5).tolist() == [0, 0, 0]
+    rng = np.random.default_rng(5)
+    s, d, t = tiny_graph(rng, 9, 300, 40, self_loops=True)
+    og = OracleGraph(s, d, t, 9)
+    g = api.Graph(s, d, t, 9)
+    # no roots
+    say("no roots")
+    assert api.count(g, api.Tree(ms, 5), roots=np.zeros(0, np.int64)).tolist() == [0, 0, 0]
+    # depth-1 tree, duplicates with other labels
+    say("depth 1 and duplicates")
+    got = api.count(g, api.Tree([[(0, 1)], [(4, 2)]], 3))
+    assert got.tolist() == [int((s != d).sum())] * 2
+    dup = [[(0, 1), (1, 2), (2, 0)], [(5, 6), (6, 7), (7, 5)], [(0, 1), (1, 0)]]
+    got = api.count(g, api.Tree(dup, 8))
+    assert got[0] == got[1] == og.count(dup[0], 8) and got[2] == og.count(dup[2], 8)
+    # window 0 and an unbounded window
+    for delta in (0, BIG, 2 ** 63 - 1):
+        say("delta", delta)
+        assert np.array_equal(api.count(g, api.Tree(ms, delta)), oracle_counts(og, ms, delta))
+    # unsorted input is sorted stably by the library
+    perm = rng.permutation(len(s))
+    say("unsorted input")
+    got = gpu_count(s[perm], d[perm], t[perm], 9, ms, 6)
+    og2 = OracleGraph(s[perm], d[perm], t[perm], 9)
+    assert np.array_equal(got, oracle_counts(og2, ms, 6))
+
+
+def test_wide_time_span_uses_64bit_times():
+    rng = np.random.default_rng(8)
+    s, d, t = tiny_graph(rng, 12, 600, 80, self_loops=False)
+    t = t * (2 ** 30) + 5          # span > 2^32
+    ms = W.random_extension_motifs(12, (2, 3, 4), 5, 2)
+    og = OracleGraph(s, d, t, 12)
+    g = api.Graph(s, d, t, 12)
+    assert g.info()["time_bytes"] == 8
+    for delta in (3 * 2 ** 30, 20 * 2 ** 30):
+        say("64-bit times", delta)
+        assert np.array_equal(api.count(g, api.Tree(ms, delta)), oracle_counts(og, ms, delta))
+
+
+def test_invalid_arguments():
+    say("invalid arguments")
+    with pytest.raises(api.MayuraError, match="MG_EINVAL"):
+        api.Graph(np.array([0, 5], np.int32), np.array([1, 1], np.int32), np.array([1, 2]), 3)
+    with pytest.raises(api.MayuraError, match="MG_EINVAL"):
+        api.Graph(np.array([0, 1], np.int32), np.array([1, 2], np.int32), np.array([5, 2]), 3,
+                  sorted_by_t=True)
+    g = api.Graph(np.array([0, 1], np.int32), np.array([1, 2], np.int32), np.array([1, 2]), 3)
+    tr = api.Tree([[(0, 1), (1, 2)]], 5)
+    with pytest.raises(api.MayuraError, match="MG_EINVAL"):
+        api.count(g, tr, roots=np.array([0, 2]))
+    with pytest.raises(api.MayuraError, match="MG_EINVAL"):
+        api.count(g, tr, chunk=100)
+    assert api.count(g, tr).tolist() == [1]

@@ -1,0 +1,94 @@
+"""Host-side logic of libmayura.so that needs no GPU: MG-Tree construction,
+relabelling, validation, and the exported C ABI."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2507_14813_amd import api, workloads as W
+from conftest import ROOT
+
+
+@pytest.fixture(scope="module")
+def L():
+    return api.lib()
+
+
+def info(motifs, delta=10):
+    return api.Tree(motifs, delta).info()
+
+
+def test_abi_exports_every_declared_symbol(L):
+    hdr = open(os.path.join(ROOT, "include", "mayura.h")).read()
+    names = set(re.findall(r"\b(mg_[a-z_]+)\s*\(", hdr))
+    names -= {"mg_alloc_fn", "mg_release_fn"}
+    assert len(names) >= 10
+    for n in sorted(names):
+        assert hasattr(L, n), n
+
+
+def test_config_trees():
+    # config 1: root C = A->B,B->C (a query), three leaves
+    i = info(W.CONFIG1_MOTIFS)
+    assert (i["n_nodes"], i["n_prefixes"], i["root_edges"], i["depth"]) == (4, 5, 2, 3)
+    assert abs(i["similarity"] - (1 - 5 / 11)) < 1e-12
+    # config 2: the 36 three-edge motifs on <= 3 vertices
+    i = info(W.enumerate_motifs(3, 3))
+    assert (i["n_nodes"], i["n_prefixes"], i["n_distinct"]) == (43, 43, 36)
+    assert abs(i["similarity"] - (1 - 43 / 108)) < 1e-12
+    # config 4: the 756 prefix-connected 3- and 4-edge motifs on <= 4 vertices
+    ms = W.enumerate_motifs(3, 4) + W.enumerate_motifs(4, 4)
+    assert len(ms) == 756
+    i = info(ms)
+    assert (i["n_nodes"], i["n_prefixes"]) == (763, 763)
+    assert abs(i["similarity"] - (1 - 763 / 2964)) < 1e-12
+
+
+def test_walkthrough_tree_shape():
+    """Section 4.3's walk-through: M3 = 3-cycle, M4 and M5 extend
+    A->B,B->C,C->D and differ in their fourth edge.  The root I1 is the
+    two-edge path with no query; its children are M3 and I2 (three-edge path,
+    no query) whose children are M4 and M5."""
+    m3 = [(0, 1), (1, 2), (2, 0)]
+    m4 = [(0, 1), (1, 2), (2, 3), (3, 0)]
+    m5 = [(0, 1), (1, 2), (2, 3), (3, 1)]
+    i = info([m3, m4, m5])
+    assert i["root_edges"] == 2 and i["n_nodes"] == 5 and i["n_prefixes"] == 6
+    # SM = 1 - (2 + 1 + 1 + 1 + 1) / 11
+    assert abs(i["similarity"] - (1 - 6 / 11)) < 1e-12
+
+
+def test_relabelling_and_duplicates():
+    a = [(0, 1), (1, 2), (2, 0)]
+    b = [(7, 3), (3, 9), (9, 7)]          # same motif, other labels
+    c = [(5, 6), (6, 5)]
+    i = info([a, b, c])
+    assert i["n_motifs"] == 3 and i["n_distinct"] == 2
+    assert info([a, c]) == {**i, "n_motifs": 2}
+
+
+@pytest.mark.parametrize("motifs,delta,status", [
+    ([[(0, 0)]], 1, "MG_EINVAL"),                       # motif self-loop
+    ([[(0, 1)]], -1, "MG_EINVAL"),                      # negative window
+    ([[(0, -2)]], 1, "MG_EINVAL"),                      # negative label
+    ([[]], 1, "MG_EINVAL"),                             # empty motif
+    ([[(0, 1)] * 6], 1, "MG_EUNSUPPORTED"),             # k > 5
+    ([[(0, 1), (2, 3), (4, 5), (6, 7)]], 1, "MG_EUNSUPPORTED"),   # > 6 vertices
+])
+def test_tree_validation(motifs, delta, status):
+    with pytest.raises(api.MayuraError) as e:
+        api.Tree(motifs, delta)
+    assert status in str(e.value)
+
+
+def test_no_motifs_rejected(L):
+    h = ctypes.c_void_p()
+    rc = L.mg_tree_create(None, None, 0, 5, ctypes.byref(h))
+    assert rc == -1 and b"no motifs" in L.mg_last_error()
+
+
+def test_count_rejects_null(L):
+    assert L.mg_count(None, None, None, None) == -1
+    L.mg_graph_destroy(None)
+    L.mg_tree_destroy(None)
