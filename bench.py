@@ -67,6 +67,10 @@ def main():
     ap.add_argument("--per-motif-steps", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--queues", type=int, default=0, help="root queues (0 = one per XCD)")
+    ap.add_argument("--chunk", type=int, default=0, help="roots per queue grab (0 = default)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the search shards by root time range with one "
@@ -80,6 +84,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        a = torch.ones(1 << 28, dtype=torch.int32, device="cuda")   # 1 GiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     t0 = time.perf_counter()
     wl = W.make_config(2, scale=args.scale)
     s, d, t, n = wl.graphs[0]
@@ -96,13 +106,14 @@ def main():
     algo_bytes = algorithmic_bytes(st, gi["time_bytes"], E)
     log("stats", st, "algorithmic bytes/launch %.3e" % algo_bytes)
 
+    kw = dict(queues=args.queues, chunk=args.chunk)
     for _ in range(args.warmup):
-        api.count(g, tr)
+        api.count(g, tr, **kw)
     torch.cuda.synchronize()
     kms = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        c, ms = api.count(g, tr, timed=True)
+        c, ms = api.count(g, tr, timed=True, **kw)
         kms.append(ms)
         if not np.array_equal(c, counts):
             raise SystemExit("counts changed between runs")
@@ -117,14 +128,16 @@ def main():
     for _ in range(args.per_motif_steps):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        c, ms = api.count(g, tr, mode="per_motif", timed=True)
+        c, ms = api.count(g, tr, mode="per_motif", timed=True, **kw)
         torch.cuda.synchronize()
         pm_wall.append(time.perf_counter() - t1)
         pm_ms.append(ms)
         if not np.array_equal(c, counts):
             raise SystemExit("per-motif counts differ from co-mined counts")
-    pm_step = sum(pm_wall) / len(pm_wall)
-    log("per-motif: %.3f ms/step wall, kernels %.3f ms" % (1e3 * pm_step, sum(pm_ms) / len(pm_ms)))
+    pm_step = sum(pm_wall) / len(pm_wall) if pm_wall else None
+    if pm_wall:
+        log("per-motif: %.3f ms/step wall, kernels %.3f ms"
+            % (1e3 * pm_step, sum(pm_ms) / len(pm_ms)))
 
     k_avg_s = sum(kms) / len(kms) / 1e3
     achieved = algo_bytes / k_avg_s / 1e9
@@ -146,10 +159,10 @@ def main():
                                % (n, E, delta),
                    "n_edges": E, "n_nodes": n, "delta": delta, "n_motifs": len(motifs),
                    "mg_tree_nodes": ti["n_nodes"], "similarity": round(ti["similarity"], 4)},
-        "speedup_vs_per_motif": pm_step / (wall / args.steps),
-        "per_motif_root_edges_per_s": E / pm_step,
+        "speedup_vs_per_motif": pm_step / (wall / args.steps) if pm_wall else None,
+        "per_motif_root_edges_per_s": E / pm_step if pm_wall else None,
         "kernel_ms": sum(kms) / len(kms),
-        "per_motif_kernel_ms": sum(pm_ms) / len(pm_ms),
+        "per_motif_kernel_ms": sum(pm_ms) / len(pm_ms) if pm_ms else None,
         "paper_context": "paper reports 2.4x (CPU, Xeon 8380) and 1.7x (GPU, A40) average "
                          "co-mining speedups on real graphs",
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,

@@ -127,13 +127,18 @@ typedef struct {
     int32_t mode;             /* MG_MODE_* */
     int32_t blocks;           /* persistent workgroups; 0 = fill the device */
     int32_t chunk;            /* roots claimed per queue grab, multiple of 64; 0 = default */
-    int32_t reserved0;
+    int32_t queues;           /* root queues: 0 = one per XCD (8), else 1..8 */
     void *stream;             /* hipStream_t */
     const int64_t *roots;     /* host: root positions to search from; NULL = all */
     int64_t n_roots;
     float *elapsed_ms;        /* optional out: device time of the search kernel(s) */
     uint64_t *stats;          /* optional out, MG_NSTATS entries: search statistics
                                  (runs an instrumented kernel; not for timing) */
+    uint64_t *root_cost;      /* optional out, n_edges entries indexed by root edge:
+                                 1 + the candidate edges examined (window entries)
+                                 in the search below that root, 0 for roots not
+                                 searched; summed over motifs in per-motif mode.
+                                 Runs an instrumented kernel; exclusive with stats. */
 } mg_count_opts;
 
 /* mg_count_opts.stats entries; every one is independent of the schedule */

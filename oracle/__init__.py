@@ -62,7 +62,7 @@ def _bind(lib):
     lib.oracle_graph_free.argtypes = [p]
     lib.oracle_graph_free.restype = None
     lib.oracle_graph_count.argtypes = [p, ctypes.c_int32, p, ctypes.c_int64, p,
-                                       ctypes.c_int64, p, p, p, ctypes.c_int32, p]
+                                       ctypes.c_int64, p, p, p, p, ctypes.c_int32, p]
     lib.oracle_graph_count.restype = ctypes.c_int
     return lib
 
@@ -126,8 +126,9 @@ class OracleGraph:
         self.n_edges = len(src)
 
     def count(self, motif, delta, roots=None, per_root=False, level=False,
-              windows=False, threads=0):
-        """Like ``count``; ``windows`` adds the per-edge window-entry totals."""
+              windows=False, windows_per_root=False, threads=0):
+        """Like ``count``; ``windows`` adds the per-edge window-entry totals,
+        ``windows_per_root`` the same per root (n_roots x k)."""
         uv = np.ascontiguousarray(np.asarray(motif, dtype=np.int32).reshape(-1))
         k = len(uv) // 2
         r = None if roots is None else np.ascontiguousarray(roots, dtype=np.int64)
@@ -135,13 +136,14 @@ class OracleGraph:
         pr = np.zeros(nr, dtype=np.uint64) if per_root else None
         lv = np.zeros((nr, k), dtype=np.uint64) if level else None
         wn = np.zeros(k, dtype=np.uint64) if windows else None
+        wr = np.zeros((nr, k), dtype=np.uint64) if windows_per_root else None
         tot = np.zeros(1, dtype=np.uint64)
         rc = self._lib.oracle_graph_count(self._h, k, _ptr(uv), int(delta), _ptr(r), nr,
-                                          _ptr(pr), _ptr(lv), _ptr(wn), int(threads),
-                                          _ptr(tot))
+                                          _ptr(pr), _ptr(lv), _ptr(wn), _ptr(wr),
+                                          int(threads), _ptr(tot))
         if rc != 0:
             raise ValueError("oracle_graph_count failed with status %d" % rc)
-        if not (per_root or level or windows):
+        if not (per_root or level or windows or windows_per_root):
             return int(tot[0])
         out = [int(tot[0])]
         if per_root:
@@ -150,6 +152,8 @@ class OracleGraph:
             out.append(lv)
         if windows:
             out.append(wn)
+        if windows_per_root:
+            out.append(wr)
         return tuple(out)
 
     def close(self):

@@ -255,6 +255,7 @@ void oracle_graph_free(oracle_graph *h) {
  *               first j+1 motif edges that start at root r
  *   win       : NULL or k totals: window entries scanned for motif edge j
  *               (entry 0 stays 0: the first edge has no window)
+ *   win_root  : NULL or n_roots*k: the same per root, entry [r*k + j]
  *   threads   : OpenMP threads (<=0: library default)
  *   total     : out, the count over the chosen roots
  * Returns 0, -1 on a bad argument.
@@ -262,7 +263,7 @@ void oracle_graph_free(oracle_graph *h) {
 int oracle_graph_count(const oracle_graph *h, int32_t k, const int32_t *motif_uv,
                        int64_t delta, const int64_t *roots, int64_t n_roots,
                        uint64_t *per_root, uint64_t *level, uint64_t *win,
-                       int32_t threads, uint64_t *total) {
+                       uint64_t *win_root, int32_t threads, uint64_t *total) {
     or_motif m;
     if (!h || delta < 0 || !total) return -1;
     if (load_motif(&m, k, motif_uv)) return -1;
@@ -279,13 +280,19 @@ int oracle_graph_count(const oracle_graph *h, int32_t k, const int32_t *motif_uv
     #pragma omp parallel
     {
         uint64_t wl[OR_MAX_K] = {0};
+        uint64_t wr[OR_MAX_K];
         #pragma omp for schedule(dynamic, 64) reduction(+ : sum)
         for (int64_t r = 0; r < n_roots; r++) {
             int64_t e = roots ? roots[r] : r;
-            uint64_t c = count_root(g, &m, delta, e,
-                                    level ? level + (size_t)r * k : NULL, win ? wl : NULL);
+            for (int j = 0; j < k; j++) wr[j] = 0;
+            uint64_t c = count_root(g, &m, delta, e, level ? level + (size_t)r * k : NULL,
+                                    (win || win_root) ? wr : NULL);
             if (per_root) per_root[r] = c;
             sum += c;
+            for (int j = 0; j < k; j++) {
+                wl[j] += wr[j];
+                if (win_root) win_root[(size_t)r * k + j] = wr[j];
+            }
         }
         if (win) {
             #pragma omp critical
@@ -306,7 +313,7 @@ int oracle_count(int64_t n_edges, const int32_t *src, const int32_t *dst,
     oracle_graph *h = oracle_graph_new(n_edges, src, dst, t, n_nodes);
     if (!h) return -1;
     int rc = oracle_graph_count(h, k, motif_uv, delta, roots, n_roots, per_root, level,
-                                NULL, threads, total);
+                                NULL, NULL, threads, total);
     oracle_graph_free(h);
     return rc;
 }

@@ -8,8 +8,10 @@ There is no fallback: without the built library every call raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
 
 import numpy as np
 
@@ -46,11 +48,11 @@ class TreeInfo(ctypes.Structure):
 
 class CountOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("blocks", ctypes.c_int32),
-                ("chunk", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("queues", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("roots", ctypes.c_void_p),
                 ("n_roots", ctypes.c_int64),
                 ("elapsed_ms", ctypes.POINTER(ctypes.c_float)),
-                ("stats", ctypes.c_void_p)]
+                ("stats", ctypes.c_void_p), ("root_cost", ctypes.c_void_p)]
 
 
 STAT_NAMES = ("win_list", "win_all", "ent_list", "ent_all", "push", "credit", "roots")
@@ -62,6 +64,20 @@ _RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_
 
 _lib = None
 _callbacks = None
+# Handles still alive at interpreter exit are left to the process end:
+# releasing them would call back into a torch that is being torn down.  The
+# flag is a list so that objects keep a reference to it after module globals
+# are cleared during finalisation.
+_EXIT = [False]
+
+
+@atexit.register
+def _mark_exit():
+    _EXIT[0] = True
+
+
+def _exiting(flag=_EXIT):
+    return flag[0] or sys.is_finalizing()
 
 
 def lib():
@@ -114,8 +130,9 @@ def use_torch_allocator():
         except Exception:
             return None
 
-    def _release(ptr, stream, ctx):
-        torch.cuda.caching_allocator_delete(int(ptr))
+    def _release(ptr, stream, ctx, _done=_exiting):
+        if not _done():
+            torch.cuda.caching_allocator_delete(int(ptr))
 
     cbs = (_ALLOC_FN(_alloc), _RELEASE_FN(_release))
     _check(lib().mg_set_allocator(cbs[0], cbs[1], None))
@@ -155,6 +172,9 @@ class Graph:
                                  SORTED_BY_T if sorted_by_t else 0,
                                  _default_stream(stream), ctypes.byref(h)))
         self._h = h
+        self._L = L
+        self._done = _exiting
+        self.n_edges = len(self._src)
         del self._src, self._dst, self._t
 
     @property
@@ -167,9 +187,9 @@ class Graph:
         return {f: getattr(gi, f) for f, _ in GraphInfo._fields_}
 
     def close(self):
-        if getattr(self, "_h", None):
-            lib().mg_graph_destroy(self._h)
-            self._h = None
+        if getattr(self, "_h", None) and not self._done():
+            self._L.mg_graph_destroy(self._h)
+        self._h = None
 
     __del__ = close
 
@@ -186,6 +206,8 @@ class Tree:
         h = ctypes.c_void_p()
         _check(L.mg_tree_create(_p(uv), _p(ks), len(ks), int(delta), ctypes.byref(h)))
         self._h = h
+        self._L = L
+        self._done = _exiting
         self.n_motifs = len(ks)
 
     @property
@@ -198,21 +220,22 @@ class Tree:
         return {f: getattr(ti, f) for f, _ in TreeInfo._fields_}
 
     def close(self):
-        if getattr(self, "_h", None):
-            lib().mg_tree_destroy(self._h)
-            self._h = None
+        if getattr(self, "_h", None) and not self._done():
+            self._L.mg_tree_destroy(self._h)
+        self._h = None
 
     __del__ = close
 
 
 def count(graph: Graph, tree: Tree, mode="comine", roots=None, blocks=0, chunk=0,
-          stream=None, timed=False, stats=False):
+          queues=0, stream=None, timed=False, stats=False, root_cost=False):
     """Exact count per motif (``mg_count``), in the tree's motif order.
 
     ``mode``: "comine" (one search over the MG-Tree) or "per_motif" (one search
     per motif).  ``roots``: optional root positions (time order).  Returns a
     uint64 array; with ``timed`` also the device milliseconds; with ``stats``
-    also a dict of search statistics (instrumented kernel).
+    also a dict of search statistics; with ``root_cost`` also the per-root
+    cost log (uint64 per edge; both run instrumented kernels).
     """
     L = lib()
     o = CountOpts()
@@ -220,6 +243,7 @@ def count(graph: Graph, tree: Tree, mode="comine", roots=None, blocks=0, chunk=0
     o.mode = {"comine": MODE_COMINE, "per_motif": MODE_PER_MOTIF}[mode]
     o.blocks = int(blocks)
     o.chunk = int(chunk)
+    o.queues = int(queues)
     o.stream = _default_stream(stream)
     r = None
     if roots is not None:
@@ -232,6 +256,10 @@ def count(graph: Graph, tree: Tree, mode="comine", roots=None, blocks=0, chunk=0
     st = np.zeros(len(STAT_NAMES), dtype=np.uint64)
     if stats:
         o.stats = st.ctypes.data
+    rcost = None
+    if root_cost:
+        rcost = np.zeros(max(1, graph.n_edges), dtype=np.uint64)
+        o.root_cost = rcost.ctypes.data
     out = np.zeros(tree.n_motifs, dtype=np.uint64)
     _check(L.mg_count(graph.handle, tree.handle, ctypes.byref(o), _p(out)))
     res = [out]
@@ -239,4 +267,6 @@ def count(graph: Graph, tree: Tree, mode="comine", roots=None, blocks=0, chunk=0
         res.append(float(ms.value))
     if stats:
         res.append({k: int(v) for k, v in zip(STAT_NAMES, st)})
+    if root_cost:
+        res.append(rcost[:graph.n_edges])
     return res[0] if len(res) == 1 else tuple(res)

@@ -10,31 +10,44 @@ constexpr int kVMax = 6;        // motif vertices
 constexpr int kKMax = 5;        // motif edges
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;
+constexpr int kQueues = 8;      // root queues, one per XCD
+constexpr int kQueueStride = 16;  // u64 words between queue heads (own cache line)
 
 // group direction: which adjacency list holds the candidates
 enum : int { kDirOut = 0, kDirIn = 1, kDirAll = 2 };
 
-// Trie ("search level") tables, as uploaded to the device.
-//   node[n] = {query id or -1, first group, group count, nv | internal << 8}
-//   grp[2g], grp[2g+1] = {dir | anchor << 4, child_new, tgt0..tgt5}
+// Search tables, as uploaded to the device.
+//   inode[i]  internal (non-leaf) trie node i: first group | group count << 20
+//   grp[2g], grp[2g+1]: eight words of group g:
+//     w0 = dir | anchor << 4 | nv << 8   (nv: vertices bound at the owning node)
+//     w1..w6 = child reached when the scanned endpoint is bound motif vertex 0..5
+//     w7 = child reached when the scanned endpoint(s) are new vertices
+//   A child word is 0 when there is no such child, else
+//     internal index (bits 0-15, if internal) | (query + 1) << 16 | internal << 31.
 struct DevTree {
-    const int4 *node;
-    const int4 *grp;
+    const uint32_t *inode;
+    const uint4 *grp;
     int32_t n_q;        // distinct motifs (counter slots)
     int32_t root_q;     // query id of the one-edge prefix, -1 if none
     int32_t depth;      // longest motif in edges
 };
+
+// One adjacency entry: the other endpoint and the edge time, side by side so
+// that the bisection that finds a window also brings its entries into cache.
+// Both layouts are two TT-sized words: entry i's time is ((TT *)list)[2i + 1]
+// and its endpoint is ((int32_t *)list)[i * sizeof(Entry) / 4].
+template <typename TT> struct Entry;
+template <> struct Entry<uint32_t> { int32_t v; uint32_t t; };
+template <> struct Entry<uint64_t> { int32_t v; int32_t pad; uint64_t t; };
 
 template <typename TT>
 struct DevGraph {
     const int32_t *gsrc, *gdst;   // time-sorted edge list (all edges)
     const TT *gt;
     const uint32_t *out_off;      // V+1
-    const int32_t *out_nbr;       // destination of each out-entry
-    const TT *out_t;
+    const Entry<TT> *out_adj;     // out-lists: destination, time
     const uint32_t *in_off;
-    const int32_t *in_nbr;        // source of each in-entry
-    const TT *in_t;
+    const Entry<TT> *in_adj;      // in-lists: source, time
     uint32_t n_edges;
 };
 
@@ -45,10 +58,13 @@ struct KParams {
     TT delta_sat;                 // delta clamped to the TT range
     const uint32_t *roots;        // NULL: roots are 0..n_roots-1
     uint32_t n_roots;
-    uint32_t chunk;               // roots per queue grab
-    uint32_t *cursor;             // queue head, zeroed before launch
+    uint32_t chunk;               // roots per queue grab (multiple of 64)
+    uint32_t n_queues;            // 1..kQueues root queues
+    unsigned long long *queues;   // kQueues heads at stride kQueueStride, zeroed
     unsigned long long *counts;   // n_q, zeroed before launch
     unsigned long long *stats;    // NULL, or kStats totals (zeroed before launch)
+    unsigned long long *root_cost;  // NULL, or per root edge id: 1 + window entries
+                                    // examined below that root (zeroed before launch)
 };
 
 // search statistics (schedule independent), filled when KParams::stats is set
@@ -67,9 +83,5 @@ enum : int {
 // Returns a hipError_t value.
 template <typename TT>
 hipError_t launch_comine(const KParams<TT> &p, int blocks, hipStream_t stream);
-
-// Blocks that fill the device for this tree depth and counter count.
-template <typename TT>
-int comine_fill_blocks(int depth, int n_q);
 
 }  // namespace mg

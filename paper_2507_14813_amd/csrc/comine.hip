@@ -9,21 +9,23 @@
 //
 // How it is laid out for the hardware (not the paper's warp-per-candidate
 // design):
-//   * Every wave is an independent worker.  It grabs a chunk of root edges
-//     from a global queue (work stealing), 64 roots per batch.
+//   * Every wave is an independent worker.  Root edges are split into eight
+//     contiguous (time-ordered) queues, one per XCD; a wave grabs chunks from
+//     its XCD's queue and steals from the others when it runs dry, so roots
+//     that are close in time, and the adjacency they read, share one L2.
 //   * Partial matches are buffered per search level in LDS.  For a batch of
 //     partial matches at level L, every (partial match, child group) pair is
 //     a window of one time-sorted adjacency list: the entries with
 //     t_prev < t <= t_first + delta, found by bisection.  Children that read
 //     the same list (same direction, same anchor vertex) form one group and
 //     share one scan of the window.
-//   * The wave expands up to 64 windows at a time as one flat candidate range:
-//     lane i takes candidate c + i, finds its window by a binary search over
-//     the lanes' inclusive prefix sums (cross-lane shuffles), reads one
-//     adjacency entry, applies the structural test with predicated compares,
-//     credits the reached node's motif in LDS counters, and compacts the
-//     survivors that still have children into the next level's buffer with
-//     ballot + mbcnt.
+//   * Up to 64 non-empty windows at a time are expanded as one flat candidate
+//     range: lane i takes candidate c + i, finds its window from a 64-bit mask
+//     of window ends (LDS flags + ballot + popcount), reads one adjacency
+//     entry, finds which bound motif vertex it hits with predicated compares,
+//     picks the reached child from the group record (which also carries the
+//     child's motif id), credits LDS counters, and compacts the survivors that
+//     still have children into the next level's buffer with ballot + mbcnt.
 //   * When the next level's buffer holds 64 or more partial matches it is
 //     expanded at once (depth first over batches), so LDS use is bounded by
 //     the motif length, not by the size of the search tree.
@@ -81,14 +83,15 @@ __device__ __forceinline__ uint64_t sat_add(uint64_t a, uint64_t d) {
     return a > ~0ull - d ? ~0ull : a + d;
 }
 
-// first index in [lo, hi) whose time exceeds v (hi if none)
+// first index i in [lo, hi) with a[i << sh] > v (hi if none); sh = 1 walks
+// the time words of interleaved adjacency entries, sh = 0 a plain array
 template <typename TT>
-__device__ __forceinline__ uint32_t first_greater(const TT *__restrict__ a, uint32_t lo,
-                                                  uint32_t hi, TT v) {
+__device__ __forceinline__ uint32_t first_greater(const TT *__restrict__ a, uint32_t sh,
+                                                  uint32_t lo, uint32_t hi, TT v) {
     uint32_t n = hi - lo;
     while (n > 0) {
         uint32_t h = n >> 1;
-        if (a[lo + h] <= v) { lo += h + 1; n -= h + 1; }
+        if (a[(size_t)(lo + h) << sh] <= v) { lo += h + 1; n -= h + 1; }
         else n = h;
     }
     return lo;
@@ -96,51 +99,77 @@ __device__ __forceinline__ uint32_t first_greater(const TT *__restrict__ a, uint
 
 // same, by exponential probing from lo (windows are short next to their lists)
 template <typename TT>
-__device__ __forceinline__ uint32_t gallop_greater(const TT *__restrict__ a, uint32_t lo,
-                                                   uint32_t hi, TT v) {
+__device__ __forceinline__ uint32_t gallop_greater(const TT *__restrict__ a, uint32_t sh,
+                                                   uint32_t lo, uint32_t hi, TT v) {
     uint64_t step = 1;
     for (;;) {
         uint64_t probe = (uint64_t)lo + step - 1;
-        if (probe >= hi) return first_greater(a, lo, hi, v);
-        if (a[probe] > v) return first_greater(a, lo, (uint32_t)probe, v);
+        if (probe >= hi) return first_greater(a, sh, lo, hi, v);
+        if (a[(size_t)probe << sh] > v) return first_greater(a, sh, lo, (uint32_t)probe, v);
         lo = (uint32_t)probe + 1;
         step <<= 1;
     }
 }
 
-__device__ __forceinline__ int32_t pick6(int y, int32_t a, int32_t b, int32_t c, int32_t d,
-                                         int32_t e, int32_t f) {
-    int32_t r = a;
-    r = (y == 1) ? b : r;
-    r = (y == 2) ? c : r;
-    r = (y == 3) ? d : r;
-    r = (y == 4) ? e : r;
-    r = (y == 5) ? f : r;
+template <typename TT>
+__device__ __forceinline__ const TT *times_of(const Entry<TT> *adj) {
+    return reinterpret_cast<const TT *>(adj) + 1;   // word 2i+1 is entry i's time
+}
+
+// child word of a group for scanned-endpoint index y (0..5 bound, else new)
+__device__ __forceinline__ uint32_t child_word(const uint4 &a, const uint4 &b, int y) {
+    uint32_t r = b.w;             // new vertex
+    r = (y == 0) ? a.y : r;
+    r = (y == 1) ? a.z : r;
+    r = (y == 2) ? a.w : r;
+    r = (y == 3) ? b.x : r;
+    r = (y == 4) ? b.y : r;
+    r = (y == 5) ? b.z : r;
     return r;
 }
 
-// Partial matches with L motif edges matched (L = 1: the root batch).
-template <typename TT, int L>
+// Partial matches with L motif edges matched.  Level 1 is the root batch:
+// every entry is at the trie root and its last edge is its first, so it keeps
+// only the two bound vertices and the root time.
+// (R: the per-root cost log keeps each partial match's root edge.)
+template <typename TT, int L, bool R>
 struct LevelBuf {
     static constexpr int S = (2 * L < kVMax) ? 2 * L : kVMax;   // vertex slots
-    static constexpr int C = (L == 1) ? kWave : 2 * kWave;       // capacity
+    static constexpr int C = 2 * kWave;                          // capacity
     int32_t phi[S][C];     // phi[s][i]: graph vertex of motif vertex s
     TT tfirst[C];
     TT tprev[C];
-    int32_t node[C];       // trie node reached
-    uint32_t pincl[C];     // inclusive prefix of child-group counts
+    uint16_t node[C];      // internal trie node reached
+    uint16_t pincl[C];     // inclusive prefix of child-group counts
+    uint32_t root[R ? C : 1];
+};
+template <typename TT, bool R>
+struct LevelBuf<TT, 1, R> {
+    static constexpr int S = 2;
+    static constexpr int C = kWave;
+    int32_t phi[2][kWave];
+    TT tfirst[kWave];
+    uint32_t root[R ? kWave : 1];
 };
 
-template <typename TT, int D, int L>
+template <typename TT, int D, bool R, int L>
 struct LevelChain {
-    LevelBuf<TT, L> buf;
-    LevelChain<TT, D, L + 1> next;
+    LevelBuf<TT, L, R> buf;
+    LevelChain<TT, D, R, L + 1> next;
 };
-template <typename TT, int D>
-struct LevelChain<TT, D, D> {};
+template <typename TT, int D, bool R>
+struct LevelChain<TT, D, R, D> {};
 
-template <int L, typename TT, int D, int M>
-__device__ __forceinline__ LevelBuf<TT, L> &lvl(LevelChain<TT, D, M> &c) {
+// per-wave LDS: level buffers plus two 64-byte scratch tables
+template <typename TT, int D, bool R>
+struct WaveLds {
+    uint8_t src[kWave];           // window compaction: lane holding the k-th window
+    uint8_t flag[kWave];          // window-end marks of one pass
+    LevelChain<TT, D, R, 1> lv;
+};
+
+template <int L, typename TT, int D, bool R, int M>
+__device__ __forceinline__ LevelBuf<TT, L, R> &lvl(LevelChain<TT, D, R, M> &c) {
     if constexpr (L == M) return c.buf;
     else return lvl<L>(c.next);
 }
@@ -150,30 +179,39 @@ struct Stats {
     uint64_t v[kStats];
 };
 
-template <typename TT, int D, bool STATS, int L>
-__device__ __forceinline__ void run_level(const KParams<TT> &p, LevelChain<TT, D, 1> &W,
+// MODE: 0 plain search, 1 with search statistics, 2 with the per-root cost log
+template <typename TT, int D, int MODE, int L>
+__device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, MODE == 2> &W,
                                           unsigned long long *cnt, const int lane,
                                           const uint32_t nA, Stats &st) {
-    LevelBuf<TT, L> &A = lvl<L>(W);
-    constexpr int SA = LevelBuf<TT, L>::S;
-    const int4 *__restrict__ node = p.tree.node;
-    const int4 *__restrict__ grp = p.tree.grp;
+    constexpr bool STATS = MODE == 1, LOG = MODE == 2;
+    LevelBuf<TT, L, LOG> &A = lvl<L>(W.lv);
+    constexpr int SA = LevelBuf<TT, L, LOG>::S;
+    const uint32_t *__restrict__ inode = p.tree.inode;
+    const uint4 *__restrict__ grp = p.tree.grp;
+    const uint64_t le_mask = (lane == 63) ? ~0ull : ((2ull << lane) - 1);
 
-    // child groups per buffered partial match -> inclusive prefix
+    // child groups per buffered partial match -> inclusive prefix (at the
+    // root level every entry has the root's groups)
     uint32_t P = 0;
-    for (uint32_t x0 = 0; x0 < nA; x0 += kWave) {
-        const uint32_t x = x0 + lane;
-        uint32_t ng = 0;
-        if (x < nA) ng = (uint32_t)node[A.node[x]].z;
-        const uint32_t incl = incl_scan32(ng, lane) + P;
-        if (x < nA) A.pincl[x] = incl;
-        P = uniform(__shfl(incl, kWave - 1));
+    const uint32_t root_ng = inode[0] >> 20;
+    if constexpr (L == 1) {
+        P = nA * root_ng;
+    } else {
+        for (uint32_t x0 = 0; x0 < nA; x0 += kWave) {
+            const uint32_t x = x0 + lane;
+            uint32_t ng = 0;
+            if (x < nA) ng = inode[A.node[x]] >> 20;
+            const uint32_t incl = incl_scan32(ng, lane) + P;
+            if (x < nA) A.pincl[x] = (uint16_t)incl;
+            P = uniform(__shfl(incl, kWave - 1));
+        }
+        wave_sync();
     }
-    wave_sync();
 
-    // window chunk state: lane w holds window w of the chunk
-    uint32_t wx = 0, wlo = 0, wincl = 0, wexcl = 0;
-    int32_t wg = 0;
+    // window chunk: lane w < nw holds non-empty window w
+    //   wrec = {entry | group << 8, first list index, exclusive start, inclusive end}
+    uint4 wrec = make_uint4(0, 0, 0, 0);
     uint32_t pc = 0, nw = 0, T = 0, cc = 0;
     uint32_t nB = 0;   // partial matches buffered at level L+1
 
@@ -185,128 +223,147 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, LevelChain<TT, D
             } else {
                 // one (partial match, group) pair per lane -> its window
                 const uint32_t pi = pc + lane;
-                uint32_t len = 0;
-                wx = 0; wlo = 0; wg = 0;
+                uint32_t len = 0, x = 0, g = 0, l0 = 0;
+                bool all = false;
                 if (pi < P) {
-                    uint32_t lo = 0, n = nA;
-                    while (n > 0) {
-                        const uint32_t h = n >> 1;
-                        if (A.pincl[lo + h] <= pi) { lo += h + 1; n -= h + 1; }
-                        else n = h;
-                    }
-                    wx = lo;
-                    const uint32_t before = lo ? A.pincl[lo - 1] : 0u;
-                    const int4 nd = node[A.node[lo]];
-                    wg = nd.y + (int32_t)(pi - before);
-                    const int4 g0 = grp[2 * wg];
-                    const int dir = g0.x & 15, anc = g0.x >> 4;
-                    const TT tp = A.tprev[lo];
-                    const TT thi = sat_add(A.tfirst[lo], p.delta_sat);
-                    uint32_t b, e;
-                    const TT *ta;
-                    if (dir == kDirOut) {
-                        const int32_t a = A.phi[anc][lo];
-                        b = p.g.out_off[a]; e = p.g.out_off[a + 1]; ta = p.g.out_t;
-                    } else if (dir == kDirIn) {
-                        const int32_t a = A.phi[anc][lo];
-                        b = p.g.in_off[a]; e = p.g.in_off[a + 1]; ta = p.g.in_t;
+                    uint32_t lo = 0;
+                    TT tp;
+                    if constexpr (L == 1) {
+                        lo = pi / root_ng;
+                        g = (inode[0] & 0xfffffu) + (pi - lo * root_ng);
+                        tp = A.tfirst[lo];
                     } else {
-                        b = 0; e = p.g.n_edges; ta = p.g.gt;
+                        uint32_t n = nA;
+                        while (n > 0) {
+                            const uint32_t h = n >> 1;
+                            if (A.pincl[lo + h] <= pi) { lo += h + 1; n -= h + 1; }
+                            else n = h;
+                        }
+                        const uint32_t before = lo ? A.pincl[lo - 1] : 0u;
+                        g = (inode[A.node[lo]] & 0xfffffu) + (pi - before);
+                        tp = A.tprev[lo];
                     }
-                    const uint32_t l0 = first_greater(ta, b, e, tp);
-                    const uint32_t l1 = gallop_greater(ta, l0, e, thi);
-                    wlo = l0;
-                    len = l1 - l0;
+                    x = lo;
+                    const uint32_t hdr = grp[2 * g].x;
+                    const int dir = hdr & 15, anc = (hdr >> 4) & 15;
+                    const TT thi = sat_add(A.tfirst[lo], p.delta_sat);
+                    uint32_t b, e, sh;
+                    const TT *ta;
+                    if (dir == kDirAll) {
+                        b = 0; e = p.g.n_edges; ta = p.g.gt; sh = 0;
+                        all = true;
+                    } else {
+                        const int32_t a = A.phi[anc][lo];
+                        const uint32_t *off = dir == kDirOut ? p.g.out_off : p.g.in_off;
+                        b = off[a]; e = off[a + 1];
+                        ta = times_of(dir == kDirOut ? p.g.out_adj : p.g.in_adj);
+                        sh = 1;
+                    }
+                    l0 = first_greater(ta, sh, b, e, tp);
+                    len = gallop_greater(ta, sh, l0, e, thi) - l0;
                 }
-                // keep the chunk's candidate total below 2^31
+                // take the longest prefix of pairs whose candidates stay below 2^31
                 const uint64_t incl64 = incl_scan64((uint64_t)len, lane);
-                const bool mine = pi < P && incl64 <= kChunkLimit;
-                const uint64_t take = __ballot(mine);
+                const bool take = pi < P && incl64 <= kChunkLimit;
+                pc += uniform((uint32_t)__popcll(__ballot(take)));
                 if constexpr (STATS) {
-                    if (mine) {
-                        const bool all = (grp[2 * wg].x & 15) == kDirAll;
+                    if (take) {
                         st.v[all ? kStatWinAll : kStatWinList] += 1;
                         st.v[all ? kStatEntAll : kStatEntList] += len;
                     }
                 }
-                nw = uniform((uint32_t)__popcll(take));
-                wincl = (uint32_t)incl64;
-                wexcl = wincl - len;
-                T = uniform(__shfl(wincl, (int)nw - 1));
+                if constexpr (LOG) {
+                    if (take && len > 0)
+                        atomicAdd(&p.root_cost[A.root[x]], (unsigned long long)len);
+                }
+                // compact the non-empty windows into lanes 0..nw-1
+                const bool keep = take && len > 0;
+                const uint64_t km = __ballot(keep);
+                nw = uniform((uint32_t)__popcll(km));
+                if (keep) W.src[mbcnt(km)] = (uint8_t)lane;
+                wave_sync();
+                const int from = (uint32_t)lane < nw ? (int)W.src[lane] : lane;
+                wave_sync();
+                const uint32_t incl = (uint32_t)incl64;
+                wrec.x = __shfl(x | (g << 8), from);
+                wrec.y = __shfl(l0, from);
+                wrec.z = __shfl(incl - len, from);
+                wrec.w = __shfl(incl, from);
+                if ((uint32_t)lane >= nw) wrec = make_uint4(0, 0, 0, 0);
+                T = nw ? uniform(__shfl(wrec.w, (int)nw - 1)) : 0u;
                 cc = 0;
-                pc += nw;
             }
         }
         if (!done && cc < T) {
             const uint32_t f = cc + lane;
-            // owner window: number of windows whose inclusive end is <= f
-            uint32_t o = 0;
-#pragma unroll
-            for (uint32_t s = 32; s > 0; s >>= 1) {
-                const uint32_t probe = o + s - 1;
-                const uint32_t v = __shfl(wincl, (int)(probe & 63));
-                if (probe < nw && v <= f) o += s;
-            }
-            const uint32_t oi = o & 63;
-            const uint32_t ox = __shfl(wx, (int)oi);
-            const uint32_t olo = __shfl(wlo, (int)oi);
-            const uint32_t oex = __shfl(wexcl, (int)oi);
-            const int32_t og = __shfl(wg, (int)oi);
+            // owner window = number of windows that end at or before f
+            const uint32_t o0 = (uint32_t)__popcll(__ballot((uint32_t)lane < nw && wrec.w <= cc));
+            if ((uint32_t)lane < nw && wrec.w > cc && wrec.w - cc < (uint32_t)kWave)
+                W.flag[wrec.w - cc] = 1;
+            wave_sync();
+            const uint32_t fl = W.flag[lane];
+            W.flag[lane] = 0;
+            const uint64_t ends = __ballot(fl != 0);
+            wave_sync();
+            const int oi = (int)((o0 + (uint32_t)__popcll(ends & le_mask)) & 63);
+            const uint32_t oxg = __shfl(wrec.x, oi);
+            const uint32_t olo = __shfl(wrec.y, oi);
+            const uint32_t oex = __shfl(wrec.z, oi);
             const bool valid = f < T;
+            const uint32_t ox = oxg & 255, og = oxg >> 8;
             const uint32_t ei = olo + (f - oex);
 
-            int32_t child = -1, nv0 = -1, nv1 = -1;
+            uint32_t cw = 0;      // child word reached by this candidate
             int dir = 0;
             uint32_t nvp = 0;
+            int32_t nv0 = -1, nv1 = -1;
             int32_t ph[SA];
 #pragma unroll
             for (int s = 0; s < SA; ++s) ph[s] = 0;
+            uint4 ga = make_uint4(0, 0, 0, 0), gb = ga;
             if (valid) {
-                const int4 g0 = grp[2 * og];
-                dir = g0.x & 15;
-                nvp = (uint32_t)(node[A.node[ox]].w & 255);
+                ga = grp[2 * og];
+                gb = grp[2 * og + 1];
+                dir = ga.x & 15;
+                nvp = (ga.x >> 8) & 15;
 #pragma unroll
                 for (int s = 0; s < SA; ++s) ph[s] = A.phi[s][ox];
-                if (dir == kDirOut) {
-                    const int4 g1 = grp[2 * og + 1];
-                    const int32_t cd = p.g.out_nbr[ei];
+                if (dir != kDirAll) {
+                    const Entry<TT> *adj = dir == kDirOut ? p.g.out_adj : p.g.in_adj;
+                    const int32_t v = adj[ei].v;
                     int y = -1;
 #pragma unroll
-                    for (int s = 0; s < SA; ++s) y = ((uint32_t)s < nvp && ph[s] == cd) ? s : y;
-                    child = (y < 0) ? g0.y : pick6(y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w);
-                    nv0 = cd;
-                } else if (dir == kDirIn) {
-                    const int32_t cs = p.g.in_nbr[ei];
-                    bool hit = false;
-#pragma unroll
-                    for (int s = 0; s < SA; ++s) hit |= ((uint32_t)s < nvp && ph[s] == cs);
-                    child = hit ? -1 : g0.y;
-                    nv0 = cs;
-                } else {
+                    for (int s = 0; s < SA; ++s) y = ((uint32_t)s < nvp && ph[s] == v) ? s : y;
+                    // in-groups have no bound-target children, so their words are 0
+                    cw = child_word(ga, gb, y);
+                    nv0 = v;
+                }
+            }
+            if (__ballot(valid && dir == kDirAll)) {
+                if (valid && dir == kDirAll) {
                     const int32_t cs = p.g.gsrc[ei], cd = p.g.gdst[ei];
                     bool hit = cs == cd;
 #pragma unroll
                     for (int s = 0; s < SA; ++s)
                         hit |= ((uint32_t)s < nvp && (ph[s] == cs || ph[s] == cd));
-                    child = hit ? -1 : g0.y;
+                    cw = hit ? 0u : gb.w;
                     nv0 = cs;
                     nv1 = cd;
                 }
             }
-            int cw = 0;
-            if (child >= 0) {
-                const int4 cn = node[child];
-                cw = cn.w;
-                if (cn.x >= 0) atomicAdd(&cnt[cn.x], 1ull);
+            if (cw) {
+                const uint32_t q1 = (cw >> 16) & 0x7fffu;
+                if (q1) atomicAdd(&cnt[q1 - 1], 1ull);
                 if constexpr (STATS) st.v[kStatCredit] += 1;
             }
             if constexpr (L + 1 < D) {
-                LevelBuf<TT, L + 1> &B = lvl<L + 1>(W);
-                constexpr int SB = LevelBuf<TT, L + 1>::S;
-                const bool push = child >= 0 && ((cw >> 8) & 1);
+                LevelBuf<TT, L + 1, LOG> &B = lvl<L + 1>(W.lv);
+                constexpr int SB = LevelBuf<TT, L + 1, LOG>::S;
+                const bool push = (cw >> 31) != 0;
                 const uint64_t pm = __ballot(push);
                 if (push) {
-                    const TT *ta = dir == kDirOut ? p.g.out_t : (dir == kDirIn ? p.g.in_t : p.g.gt);
+                    const TT tnew = dir == kDirAll ? p.g.gt[ei]
+                                    : (dir == kDirOut ? p.g.out_adj : p.g.in_adj)[ei].t;
                     const uint32_t slot = nB + mbcnt(pm);
 #pragma unroll
                     for (int s = 0; s < SB; ++s) {
@@ -316,8 +373,9 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, LevelChain<TT, D
                         B.phi[s][slot] = v;
                     }
                     B.tfirst[slot] = A.tfirst[ox];
-                    B.tprev[slot] = ta[ei];
-                    B.node[slot] = child;
+                    B.tprev[slot] = tnew;
+                    B.node[slot] = (uint16_t)(cw & 0xffffu);
+                    if constexpr (LOG) B.root[slot] = A.root[ox];
                     if constexpr (STATS) st.v[kStatPush] += 1;
                 }
                 nB += (uint32_t)__popcll(pm);
@@ -327,7 +385,7 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, LevelChain<TT, D
         if constexpr (L + 1 < D) {
             if (nB >= kWave || (done && nB > 0)) {
                 wave_sync();
-                run_level<TT, D, STATS, L + 1>(p, W, cnt, lane, nB, st);
+                run_level<TT, D, MODE, L + 1>(p, W, cnt, lane, nB, st);
                 wave_sync();
                 nB = 0;
             }
@@ -336,60 +394,72 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, LevelChain<TT, D
     }
 }
 
-template <typename TT, int D, bool STATS>
+template <typename TT, int D, int MODE>
 __global__ void __launch_bounds__(kWave * kWavesPerBlock)
 comine_kernel(const KParams<TT> p) {
+    constexpr bool STATS = MODE == 1, LOG = MODE == 2;
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned long long *cnt = reinterpret_cast<unsigned long long *>(smem);
     const size_t cnt_bytes = ((size_t)p.tree.n_q * 8 + 15) & ~(size_t)15;
     const int lane = (int)(threadIdx.x & (kWave - 1));
     const int wave = (int)(threadIdx.x / kWave);
-    LevelChain<TT, D, 1> &W =
-        reinterpret_cast<LevelChain<TT, D, 1> *>(smem + cnt_bytes)[wave];
+    WaveLds<TT, D, LOG> &W = reinterpret_cast<WaveLds<TT, D, LOG> *>(smem + cnt_bytes)[wave];
 
     for (int i = (int)threadIdx.x; i < p.tree.n_q; i += (int)blockDim.x) cnt[i] = 0;
+    W.flag[lane] = 0;
     __syncthreads();
     Stats st;
 #pragma unroll
     for (int i = 0; i < kStats; ++i) st.v[i] = 0;
 
-    for (;;) {
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(p.cursor, p.chunk);
-        base = uniform(__shfl(base, 0));
-        if (base >= p.n_roots) break;
-        const uint32_t end = min(base + p.chunk, p.n_roots);
-        for (uint32_t b = base; b < end; b += kWave) {
-            const uint32_t i = b + (uint32_t)lane;
-            bool ok = i < end;
-            uint32_t r = 0;
-            int32_t s = 0, d = 0;
-            if (ok) {
-                r = p.roots ? p.roots[i] : i;
-                s = p.g.gsrc[r];
-                d = p.g.gdst[r];
-                ok = s != d;
-            }
-            const uint64_t m = __ballot(ok);
-            if (p.tree.root_q >= 0 && lane == 0 && m)
-                atomicAdd(&cnt[p.tree.root_q], (unsigned long long)__popcll(m));
-            if constexpr (STATS) st.v[kStatRoots] += ok ? 1 : 0;
-            if constexpr (D > 1) {
-                LevelBuf<TT, 1> &A = lvl<1>(W);
+    // workgroups are dispatched to the XCDs round-robin: start on this XCD's
+    // share of the roots, then take what is left of the others
+    const uint32_t nq = p.n_queues;
+    const uint32_t home = blockIdx.x % nq;
+    for (uint32_t qi = 0; qi < nq; ++qi) {
+        const uint32_t q = (home + qi) % nq;
+        const uint32_t qbeg = (uint32_t)(((uint64_t)p.n_roots * q) / nq);
+        const uint32_t qend = (uint32_t)(((uint64_t)p.n_roots * (q + 1)) / nq);
+        for (;;) {
+            unsigned long long got = 0;
+            if (lane == 0) got = atomicAdd(&p.queues[q * kQueueStride], (unsigned long long)p.chunk);
+            got = __shfl(got, 0);
+            if (got >= (unsigned long long)(qend - qbeg)) break;
+            const uint32_t base = uniform(qbeg + (uint32_t)got);
+            const uint32_t end = min(base + p.chunk, qend);
+            for (uint32_t b = base; b < end; b += kWave) {
+                const uint32_t i = b + (uint32_t)lane;
+                bool ok = i < end;
+                uint32_t r = 0;
+                int32_t s = 0, d = 0;
                 if (ok) {
-                    const uint32_t slot = mbcnt(m);
-                    const TT tr = p.g.gt[r];
-                    A.phi[0][slot] = s;
-                    A.phi[1][slot] = d;
-                    A.tfirst[slot] = tr;
-                    A.tprev[slot] = tr;
-                    A.node[slot] = 0;
+                    r = p.roots ? p.roots[i] : i;
+                    s = p.g.gsrc[r];
+                    d = p.g.gdst[r];
+                    ok = s != d;
                 }
-                const uint32_t n1 = uniform((uint32_t)__popcll(m));
-                if (n1 > 0) {
-                    wave_sync();
-                    run_level<TT, D, STATS, 1>(p, W, cnt, lane, n1, st);
-                    wave_sync();
+                const uint64_t m = __ballot(ok);
+                if (p.tree.root_q >= 0 && lane == 0 && m)
+                    atomicAdd(&cnt[p.tree.root_q], (unsigned long long)__popcll(m));
+                if constexpr (STATS) st.v[kStatRoots] += ok ? 1 : 0;
+                if constexpr (LOG) {
+                    if (ok) atomicAdd(&p.root_cost[r], 1ull);
+                }
+                if constexpr (D > 1) {
+                    LevelBuf<TT, 1, LOG> &A = lvl<1>(W.lv);
+                    if (ok) {
+                        const uint32_t slot = mbcnt(m);
+                        A.phi[0][slot] = s;
+                        A.phi[1][slot] = d;
+                        A.tfirst[slot] = p.g.gt[r];
+                        if constexpr (LOG) A.root[slot] = r;
+                    }
+                    const uint32_t n1 = uniform((uint32_t)__popcll(m));
+                    if (n1 > 0) {
+                        wave_sync();
+                        run_level<TT, D, MODE, 1>(p, W, cnt, lane, n1, st);
+                        wave_sync();
+                    }
                 }
             }
         }
@@ -405,16 +475,16 @@ comine_kernel(const KParams<TT> p) {
         if (cnt[i]) atomicAdd(&p.counts[i], cnt[i]);
 }
 
-template <typename TT, int D>
+template <typename TT, int D, int MODE>
 size_t smem_bytes(int n_q) {
     return (((size_t)n_q * 8 + 15) & ~(size_t)15) +
-           (size_t)kWavesPerBlock * sizeof(LevelChain<TT, D, 1>);
+           (size_t)kWavesPerBlock * sizeof(WaveLds<TT, D, MODE == 2>);
 }
 
-template <typename TT, int D, bool STATS>
+template <typename TT, int D, int MODE>
 hipError_t launch_ds(const KParams<TT> &p, int blocks, hipStream_t stream) {
-    const size_t sm = smem_bytes<TT, D>(p.tree.n_q);
-    auto kern = comine_kernel<TT, D, STATS>;
+    const size_t sm = smem_bytes<TT, D, MODE>(p.tree.n_q);
+    auto kern = comine_kernel<TT, D, MODE>;
     if (sm > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)kern,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
@@ -436,21 +506,9 @@ hipError_t launch_ds(const KParams<TT> &p, int blocks, hipStream_t stream) {
 
 template <typename TT, int D>
 hipError_t launch_d(const KParams<TT> &p, int blocks, hipStream_t stream) {
-    return p.stats ? launch_ds<TT, D, true>(p, blocks, stream)
-                   : launch_ds<TT, D, false>(p, blocks, stream);
-}
-
-template <typename TT, int D>
-int fill_d(int n_q) {
-    int dev = 0, ncu = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, comine_kernel<TT, D, false>,
-                                                     kWave * kWavesPerBlock,
-                                                     smem_bytes<TT, D>(n_q)) != hipSuccess)
-        return 0;
-    return ncu * per;
+    if (p.stats) return launch_ds<TT, D, 1>(p, blocks, stream);
+    if (p.root_cost) return launch_ds<TT, D, 2>(p, blocks, stream);
+    return launch_ds<TT, D, 0>(p, blocks, stream);
 }
 
 }  // namespace
@@ -467,21 +525,7 @@ hipError_t launch_comine(const KParams<TT> &p, int blocks, hipStream_t stream) {
     }
 }
 
-template <typename TT>
-int comine_fill_blocks(int depth, int n_q) {
-    switch (depth) {
-        case 1: return fill_d<TT, 1>(n_q);
-        case 2: return fill_d<TT, 2>(n_q);
-        case 3: return fill_d<TT, 3>(n_q);
-        case 4: return fill_d<TT, 4>(n_q);
-        case 5: return fill_d<TT, 5>(n_q);
-        default: return 0;
-    }
-}
-
 template hipError_t launch_comine<uint32_t>(const KParams<uint32_t> &, int, hipStream_t);
 template hipError_t launch_comine<uint64_t>(const KParams<uint64_t> &, int, hipStream_t);
-template int comine_fill_blocks<uint32_t>(int, int);
-template int comine_fill_blocks<uint64_t>(int, int);
 
 }  // namespace mg

@@ -19,6 +19,7 @@
 
 using mg::kVMax;
 using mg::kKMax;
+constexpr size_t kQueueBytes = sizeof(unsigned long long) * mg::kQueues * mg::kQueueStride;
 
 namespace {
 
@@ -95,11 +96,10 @@ struct mg_graph {
     int64_t t_min = 0, t_max = 0;
     int time_bytes = 4;
     int device = 0;
-    DevBuf gsrc, gdst, gt, out_off, out_nbr, out_t, in_off, in_nbr, in_t;
+    DevBuf gsrc, gdst, gt, out_off, out_adj, in_off, in_adj;
     int64_t device_bytes = 0;
     ~mg_graph() {
-        for (DevBuf *b : {&gsrc, &gdst, &gt, &out_off, &out_nbr, &out_t, &in_off, &in_nbr, &in_t})
-            dev_free(*b);
+        for (DevBuf *b : {&gsrc, &gdst, &gt, &out_off, &out_adj, &in_off, &in_adj}) dev_free(*b);
     }
 };
 
@@ -120,16 +120,17 @@ int upload_graph(mg_graph *g, const std::vector<int32_t> &s, const std::vector<i
         if (s[i] != d[i]) { oo[s[i] + 1]++; io[d[i] + 1]++; }
     for (int32_t v = 0; v < V; ++v) { oo[v + 1] += oo[v]; io[v + 1] += io[v]; }
     const uint32_t A = oo[V];
-    std::vector<int32_t> on(A), in_(A);
-    std::vector<TT> ot(A), it(A);
+    std::vector<mg::Entry<TT>> oadj(A), iadj(A);
     {
         std::vector<uint32_t> po(oo.begin(), oo.end() - 1), pi(io.begin(), io.end() - 1);
         for (int64_t i = 0; i < E; ++i) {
             if (s[i] == d[i]) continue;
-            uint32_t a = po[s[i]]++;
-            on[a] = d[i]; ot[a] = rt[i];
-            uint32_t b = pi[d[i]]++;
-            in_[b] = s[i]; it[b] = rt[i];
+            mg::Entry<TT> &x = oadj[po[s[i]]++];
+            std::memset(&x, 0, sizeof x);
+            x.v = d[i]; x.t = rt[i];
+            mg::Entry<TT> &y = iadj[pi[d[i]]++];
+            std::memset(&y, 0, sizeof y);
+            y.v = s[i]; y.t = rt[i];
         }
     }
     struct Up { DevBuf *b; const void *h; size_t n; };
@@ -137,9 +138,9 @@ int upload_graph(mg_graph *g, const std::vector<int32_t> &s, const std::vector<i
         {&g->gsrc, s.data(), sizeof(int32_t) * E}, {&g->gdst, d.data(), sizeof(int32_t) * E},
         {&g->gt, rt.data(), sizeof(TT) * E},
         {&g->out_off, oo.data(), sizeof(uint32_t) * (V + 1)},
-        {&g->out_nbr, on.data(), sizeof(int32_t) * A}, {&g->out_t, ot.data(), sizeof(TT) * A},
+        {&g->out_adj, oadj.data(), sizeof(mg::Entry<TT>) * A},
         {&g->in_off, io.data(), sizeof(uint32_t) * (V + 1)},
-        {&g->in_nbr, in_.data(), sizeof(int32_t) * A}, {&g->in_t, it.data(), sizeof(TT) * A},
+        {&g->in_adj, iadj.data(), sizeof(mg::Entry<TT>) * A},
     };
     g->device_bytes = 0;
     for (auto &u : ups) {
@@ -176,8 +177,8 @@ struct mg_tree {
     std::vector<int32_t> motif_q;       // caller motif -> distinct id
     std::vector<Motif> distinct;
     std::vector<TrieNode> nodes;        // node 0 = prefix ((0,1))
-    std::vector<int32_t> node_tab;      // 4 ints per node
-    std::vector<int32_t> grp_tab;       // 8 ints per group
+    std::vector<int32_t> node_tab;      // one word per internal node
+    std::vector<int32_t> grp_tab;       // 8 words per group
     int32_t depth = 0, root_q = -1;
     mg_tree_info_t info{};
     // device copies
@@ -241,14 +242,27 @@ int build_tree(mg_tree *tr) {
         }
         tr->nodes[cur].q = (int)q;
     }
-    // flat tables: BFS order is creation order already (parents first)
+    // flat tables (see comine.h): internal nodes get dense indices, the
+    // root (node 0) being internal index 0 whenever it has children
     const int N = (int)tr->nodes.size();
-    tr->node_tab.assign(4 * N, 0);
+    std::vector<int> iidx(N, -1);
+    int n_int = 0;
+    for (int n = 0; n < N; ++n)
+        if (!tr->nodes[n].kids.empty()) iidx[n] = n_int++;
+    if (n_int > 0xffff) return fail(MG_EUNSUPPORTED, "%d internal search nodes (limit 65535)", n_int);
+    auto child_word = [&](int c) -> int32_t {
+        const TrieNode &ch = tr->nodes[c];
+        uint32_t w = ((uint32_t)(ch.q + 1) & 0x7fffu) << 16;
+        if (iidx[c] >= 0) w |= (uint32_t)iidx[c] | 0x80000000u;
+        return (int32_t)w;
+    };
+    tr->node_tab.assign(n_int > 0 ? n_int : 1, 0);
     tr->grp_tab.clear();
     tr->depth = 0;
     for (int n = 0; n < N; ++n) {
         const TrieNode &nd = tr->nodes[n];
         tr->depth = std::max(tr->depth, nd.depth);
+        if (nd.kids.empty()) continue;
         // group the children by the list they scan
         std::map<std::pair<int, int>, std::vector<int>> groups;
         for (int c : nd.kids) {
@@ -260,21 +274,24 @@ int build_tree(mg_tree *tr) {
             groups[{dir, anc}].push_back(c);
         }
         const int g0 = (int)tr->grp_tab.size() / 8;
+        if (g0 + (int)groups.size() > (1 << 20))
+            return fail(MG_EUNSUPPORTED, "too many child groups");
         for (auto &kv : groups) {
-            int32_t rec[8] = {kv.first.first | (kv.first.second << 4), -1, -1, -1, -1, -1, -1, -1};
+            int32_t rec[8] = {kv.first.first | (kv.first.second << 4) | (nd.nv << 8),
+                              0, 0, 0, 0, 0, 0, 0};
             for (int c : kv.second) {
                 const TrieNode &ch = tr->nodes[c];
-                if (kv.first.first == mg::kDirOut && ch.v < nd.nv) rec[2 + ch.v] = c;
-                else rec[1] = c;   // edge to a new vertex (or two new vertices)
+                // out-group: the scanned endpoint is the destination; a bound
+                // destination selects word 1+v, a new one word 7.  In- and
+                // whole-list groups only ever reach new vertices (word 7).
+                if (kv.first.first == mg::kDirOut && ch.v < nd.nv) rec[1 + ch.v] = child_word(c);
+                else rec[7] = child_word(c);
             }
             tr->grp_tab.insert(tr->grp_tab.end(), rec, rec + 8);
         }
-        tr->node_tab[4 * n + 0] = nd.q;
-        tr->node_tab[4 * n + 1] = g0;
-        tr->node_tab[4 * n + 2] = (int)groups.size();
-        tr->node_tab[4 * n + 3] = nd.nv | ((nd.kids.empty() ? 0 : 1) << 8);
+        tr->node_tab[iidx[n]] = (int32_t)((uint32_t)g0 | ((uint32_t)groups.size() << 20));
     }
-    if (tr->grp_tab.empty()) tr->grp_tab.assign(8, -1);
+    if (tr->grp_tab.empty()) tr->grp_tab.assign(8, 0);
     tr->root_q = tr->nodes[0].q;
 
     // MG-Tree view: the root is the longest prefix shared by every motif;
@@ -350,21 +367,20 @@ int upload_tree(mg_tree *tr, int device, hipStream_t st) {
 // One launch of the co-mining kernel over a tree; counts land in d_counts.
 template <typename TT>
 int launch_tree(const mg_graph *g, mg_tree *tr, const uint32_t *d_roots, uint32_t n_roots,
-                uint32_t *d_cursor, unsigned long long *d_counts, unsigned long long *d_stats,
+                unsigned long long *d_queues, unsigned long long *d_counts,
+                unsigned long long *d_stats, unsigned long long *d_cost,
                 const mg_count_opts &o, hipStream_t st, float *ms) {
     mg::KParams<TT> p{};
     p.g.gsrc = (const int32_t *)g->gsrc.ptr;
     p.g.gdst = (const int32_t *)g->gdst.ptr;
     p.g.gt = (const TT *)g->gt.ptr;
     p.g.out_off = (const uint32_t *)g->out_off.ptr;
-    p.g.out_nbr = (const int32_t *)g->out_nbr.ptr;
-    p.g.out_t = (const TT *)g->out_t.ptr;
+    p.g.out_adj = (const mg::Entry<TT> *)g->out_adj.ptr;
     p.g.in_off = (const uint32_t *)g->in_off.ptr;
-    p.g.in_nbr = (const int32_t *)g->in_nbr.ptr;
-    p.g.in_t = (const TT *)g->in_t.ptr;
+    p.g.in_adj = (const mg::Entry<TT> *)g->in_adj.ptr;
     p.g.n_edges = (uint32_t)g->E;
-    p.tree.node = (const int4 *)tr->d_node.ptr;
-    p.tree.grp = (const int4 *)tr->d_grp.ptr;
+    p.tree.inode = (const uint32_t *)tr->d_node.ptr;
+    p.tree.grp = (const uint4 *)tr->d_grp.ptr;
     p.tree.n_q = (int32_t)tr->distinct.size();
     p.tree.root_q = tr->root_q;
     p.tree.depth = tr->depth;
@@ -374,12 +390,14 @@ int launch_tree(const mg_graph *g, mg_tree *tr, const uint32_t *d_roots, uint32_
         p.delta_sat = (TT)(uint64_t)tr->delta;
     p.roots = d_roots;
     p.n_roots = n_roots;
-    p.chunk = (uint32_t)(o.chunk > 0 ? o.chunk : 256);
-    p.cursor = d_cursor;
+    p.chunk = (uint32_t)(o.chunk > 0 ? o.chunk : 64);
+    p.n_queues = (uint32_t)(o.queues > 0 ? o.queues : mg::kQueues);
+    p.queues = d_queues;
     p.counts = d_counts;
     p.stats = d_stats;
+    p.root_cost = d_cost;
 
-    HIP_TRY(hipMemsetAsync(d_cursor, 0, sizeof(uint32_t), st));
+    HIP_TRY(hipMemsetAsync(d_queues, 0, kQueueBytes, st));
     if (d_stats) HIP_TRY(hipMemsetAsync(d_stats, 0, sizeof(unsigned long long) * mg::kStats, st));
     HIP_TRY(hipMemsetAsync(d_counts, 0, sizeof(unsigned long long) * p.tree.n_q, st));
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -539,9 +557,13 @@ int mg_count(const mg_graph *g, const mg_tree *tr_c, const mg_count_opts *opts,
         if (opts) o = *opts;
         if (o.mode != MG_MODE_COMINE && o.mode != MG_MODE_PER_MOTIF)
             return fail(MG_EINVAL, "unknown mode %d", o.mode);
-        if (o.chunk < 0 || (o.chunk % 64) != 0 || o.chunk > (1 << 20))
-            return fail(MG_EINVAL, "chunk must be a multiple of 64 in [0, 2^20]");
+        if (o.chunk < 0 || (o.chunk % 64) != 0 || o.chunk > (1 << 16))
+            return fail(MG_EINVAL, "chunk must be a multiple of 64 in [0, 65536]");
         if (o.roots && o.n_roots < 0) return fail(MG_EINVAL, "n_roots < 0");
+        if (o.queues < 0 || o.queues > mg::kQueues)
+            return fail(MG_EINVAL, "queues must be in [0, %d]", mg::kQueues);
+        if (o.stats && o.root_cost)
+            return fail(MG_EINVAL, "stats and root_cost are exclusive");
         int dev = 0;
         HIP_TRY(hipGetDevice(&dev));
         if (dev != g->device) return fail(MG_EINVAL, "graph lives on device %d, current is %d",
@@ -587,15 +609,22 @@ int mg_count(const mg_graph *g, const mg_tree *tr_c, const mg_count_opts *opts,
         for (mg_tree *t : runs) maxq = std::max(maxq, t->distinct.size());
         static_assert(mg::kStats == MG_NSTATS, "stats layout");
         DevBuf d_work;
-        const size_t stats_off = 16 + 8 * maxq;
+        const size_t stats_off = kQueueBytes + 8 * maxq;
         int rc = dev_alloc(d_work, stats_off + 8 * mg::kStats, (void *)st);
         if (rc) return rc;
         struct Guard2 { DevBuf *b; ~Guard2() { dev_free(*b); } } gw{&d_work};
-        uint32_t *d_cursor = (uint32_t *)d_work.ptr;
-        unsigned long long *d_counts = (unsigned long long *)((char *)d_work.ptr + 16);
+        unsigned long long *d_queues = (unsigned long long *)d_work.ptr;
+        unsigned long long *d_counts = (unsigned long long *)((char *)d_work.ptr + kQueueBytes);
         unsigned long long *d_stats =
             o.stats ? (unsigned long long *)((char *)d_work.ptr + stats_off) : nullptr;
         std::vector<uint64_t> stats_sum(mg::kStats, 0);
+        DevBuf d_cost;
+        if (o.root_cost) {
+            rc = dev_alloc(d_cost, sizeof(uint64_t) * (size_t)g->E, (void *)st);
+            if (rc) return rc;
+            if (g->E) HIP_TRY(hipMemsetAsync(d_cost.ptr, 0, sizeof(uint64_t) * (size_t)g->E, st));
+        }
+        struct Guard3 { DevBuf *b; ~Guard3() { dev_free(*b); } } gc{&d_cost};
 
         std::vector<uint64_t> qcount(tr->distinct.size(), 0);
         float total_ms = 0.f;
@@ -606,10 +635,12 @@ int mg_count(const mg_graph *g, const mg_tree *tr_c, const mg_count_opts *opts,
             float ms = 0.f;
             rc = g->time_bytes == 4
                      ? launch_tree<uint32_t>(g, t, (const uint32_t *)d_roots.ptr, n_roots,
-                                             d_cursor, d_counts, d_stats, o, st,
+                                             d_queues, d_counts, d_stats,
+                                             (unsigned long long *)d_cost.ptr, o, st,
                                              o.elapsed_ms ? &ms : nullptr)
                      : launch_tree<uint64_t>(g, t, (const uint32_t *)d_roots.ptr, n_roots,
-                                             d_cursor, d_counts, d_stats, o, st,
+                                             d_queues, d_counts, d_stats,
+                                             (unsigned long long *)d_cost.ptr, o, st,
                                              o.elapsed_ms ? &ms : nullptr);
             if (rc) return rc;
             total_ms += ms;
@@ -625,6 +656,11 @@ int mg_count(const mg_graph *g, const mg_tree *tr_c, const mg_count_opts *opts,
             else qcount[ri] = h[0];
         }
         for (int32_t i = 0; i < tr->n_motifs; ++i) counts[i] = qcount[tr->motif_q[i]];
+        if (o.root_cost && g->E) {
+            HIP_TRY(hipMemcpyAsync(o.root_cost, d_cost.ptr, sizeof(uint64_t) * (size_t)g->E,
+                                   hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+        }
         if (o.elapsed_ms) *o.elapsed_ms = total_ms;
         if (o.stats) std::copy(stats_sum.begin(), stats_sum.end(), o.stats);
         return MG_OK;

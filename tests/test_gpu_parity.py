@@ -77,9 +77,9 @@ def test_tiny_random_graphs(seed):
         assert np.array_equal(got, want), delta
 
 
-def _medium(seed=1, E=4000, V=40, tmax=600):
+def _medium(seed=1, E=4000, V=40, tmax=600, self_loops=True):
     rng = np.random.default_rng(seed)
-    s, d, t = tiny_graph(rng, V, E, tmax, self_loops=True)
+    s, d, t = tiny_graph(rng, V, E, tmax, self_loops=self_loops)
     ms = (W.random_extension_motifs(30, (2, 3, 4, 5), 6, seed)
           + [m for m in W.enumerate_motifs(3, 6, connected=False) if max(max(e) for e in m) >= 3][:20])
     return s, d, t, V, ms
@@ -96,9 +96,9 @@ def test_medium_graph_all_modes(delta):
     say("medium", delta)
     assert np.array_equal(api.count(g, tr), want)
     assert np.array_equal(api.count(g, tr, mode="per_motif"), want)
-    for blocks, chunk in ((1, 64), (3, 128), (0, 1024), (0, 64)):
-        say("schedule", blocks, chunk)
-        assert np.array_equal(api.count(g, tr, blocks=blocks, chunk=chunk), want)
+    for blocks, chunk, queues in ((1, 64, 0), (3, 128, 1), (0, 1024, 3), (0, 64, 8), (9, 192, 0)):
+        say("schedule", blocks, chunk, queues)
+        assert np.array_equal(api.count(g, tr, blocks=blocks, chunk=chunk, queues=queues), want)
     roots = np.arange(5, len(s), 7)
     say("roots subset")
     assert np.array_equal(api.count(g, tr, roots=roots), oracle_counts(og, ms, delta, roots))
@@ -151,7 +151,9 @@ def _trie_expectations(og, motifs, delta):
 
 
 def test_search_statistics_match_oracle():
-    s, d, t, n, ms = _medium(seed=3, E=2500)
+    # per-vertex lists on the GPU leave self-loops out (they never match) while
+    # the oracle scans them, so window sizes are compared on a loop-free graph
+    s, d, t, n, ms = _medium(seed=3, E=2500, self_loops=False)
     og = OracleGraph(s, d, t, n)
     want = _trie_expectations(og, ms, 30)
     g = api.Graph(s, d, t, n)
@@ -162,6 +164,61 @@ def test_search_statistics_match_oracle():
     assert st["roots"] == int((s != d).sum())
     for k, v in want.items():
         assert st[k] == v, (k, st[k], v)
+
+
+def _root_cost_expectation(og, motifs, delta, n_edges, src, dst):
+    """Per-root search cost of co-mining from the oracle's per-root window
+    logs: 1 for the root plus, for every distinct prefix p with children and
+    every list its children scan, the window entries under that root."""
+    def canon(m):
+        lab, out = {}, []
+        for u, v in m:
+            for x in (u, v):
+                lab.setdefault(x, len(lab))
+            out.append((lab[u], lab[v]))
+        return tuple(out)
+    prefixes = {c[:j] for m in motifs for c in [canon(m)] for j in range(1, len(c) + 1)}
+    kids = {}
+    for p in prefixes:
+        if len(p) > 1:
+            kids.setdefault(p[:-1], []).append(p)
+    o = np.lexsort((np.arange(n_edges), og_times(og)))
+    cost = (src[o] != dst[o]).astype(np.uint64)
+    for p, cs in kids.items():
+        nv = 1 + max(max(e) for e in p)
+        seen = set()
+        for c in cs:
+            u, v = c[-1]
+            key = ("out", u) if u < nv else (("in", v) if v < nv else ("all", 0))
+            if key in seen:
+                continue
+            seen.add(key)
+            _, wr = og.count(list(c), delta, windows_per_root=True)
+            cost += wr[:, len(p)]
+    return cost
+
+
+def og_times(og):
+    return og.t_sorted
+
+
+def test_per_root_cost_log_matches_oracle():
+    # loop-free graph: the oracle's lists keep self-loop edges, the GPU's do not
+    s, d, t, n, ms = _medium(seed=4, E=3000, self_loops=False)
+    o = np.lexsort((np.arange(len(t)), t))
+    og = OracleGraph(s, d, t, n)
+    og.t_sorted = t[o]
+    g = api.Graph(s, d, t, n)
+    say("root cost log")
+    for delta in (9, 35):
+        tr = api.Tree(ms, delta)
+        counts, cost = api.count(g, tr, root_cost=True)
+        assert np.array_equal(counts, oracle_counts(og, ms, delta))
+        want = _root_cost_expectation(og, ms, delta, len(s), s, d)
+        assert np.array_equal(cost, want), delta
+        # per-motif mode logs the sum of the per-motif searches
+        _, cpm = api.count(g, tr, mode="per_motif", root_cost=True)
+        assert (cpm >= cost).all() and cpm.sum() > cost.sum()
 
 
 def test_config1_full():
@@ -230,6 +287,11 @@ def test_edge_cases(oracle_mod):
     # no roots
     say("no roots")
     assert api.count(g, api.Tree(ms, 5), roots=np.zeros(0, np.int64)).tolist() == [0, 0, 0]
+    # self-loop roots are never searched
+    say("root cost of self-loops")
+    _, cost = api.count(g, api.Tree(ms, 5), root_cost=True)
+    o = np.lexsort((np.arange(len(t)), t))
+    assert (cost[(s[o] == d[o])] == 0).all() and (cost[(s[o] != d[o])] >= 1).all()
     # depth-1 tree, duplicates with other labels
     say("depth 1 and duplicates")
     got = api.count(g, api.Tree([[(0, 1)], [(4, 2)]], 3))
@@ -275,4 +337,6 @@ def test_invalid_arguments():
         api.count(g, tr, roots=np.array([0, 2]))
     with pytest.raises(api.MayuraError, match="MG_EINVAL"):
         api.count(g, tr, chunk=100)
+    with pytest.raises(api.MayuraError, match="MG_EINVAL"):
+        api.count(g, tr, queues=9)
     assert api.count(g, tr).tolist() == [1]
