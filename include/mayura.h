@@ -134,6 +134,9 @@ typedef struct {
     float *elapsed_ms;        /* optional out: device time of the search kernel(s) */
     uint64_t *stats;          /* optional out, MG_NSTATS entries: search statistics
                                  (runs an instrumented kernel; not for timing) */
+    int32_t sched;            /* MG_SCHED_PLAIN (default) or MG_SCHED_LEARNED */
+    int32_t reserved1;
+    const struct mg_model *model;   /* cost model for MG_SCHED_LEARNED */
     uint64_t *root_cost;      /* optional out, n_edges entries indexed by root edge:
                                  1 + the candidate edges examined (window entries)
                                  in the search below that root, 0 for roots not
@@ -151,6 +154,12 @@ typedef struct {
 #define MG_STAT_ROOTS 6      /* root edges searched (self-loops excluded) */
 #define MG_NSTATS 7
 
+/* schedules (what runs where; never what is counted) */
+#define MG_SCHED_PLAIN 0      /* roots in time order, 64-root chunks from XCD queues */
+#define MG_SCHED_LEARNED 1    /* an MLP predicts every root's cost; time-local
+                                 64-root segments run heaviest first, costly
+                                 segments split into single roots */
+
 /* Fill opts with the defaults (co-mining, all roots, null stream). */
 void mg_count_opts_init(mg_count_opts *opts);
 
@@ -162,6 +171,82 @@ void mg_count_opts_init(mg_count_opts *opts);
  */
 int mg_count(const mg_graph *g, const mg_tree *tr, const mg_count_opts *opts,
              uint64_t *counts);
+
+/*
+ * Learned root-cost model (not in the paper): a 4-layer MLP, 16 -> 64 -> 64 ->
+ * 64 -> 1 with ReLU, BF16 weights and activations, FP32 accumulation (MFMA),
+ * that predicts log(1 + candidate edges examined below a root) -- the label
+ * mg_count_opts.root_cost logs.  Parameters are an FP32 master copy of
+ * MG_MODEL_PARAMS floats laid out as W1[32][64] (rows 16..31 zero), b1[64],
+ * W2[64][64], b2[64], W3[64][64], b3[64], W4[64], b4 (row-major [in][out]).
+ * All model calls run on the null stream and return when done.
+ */
+#define MG_NFEATURES 16
+#define MG_MODEL_PARAMS 10497
+typedef struct mg_model mg_model;  /* opaque */
+/* He-initialised weights from a seeded generator, zero biases. */
+int mg_model_create(uint64_t seed, mg_model **out);
+int mg_model_get_weights(const mg_model *m, float *w /* MG_MODEL_PARAMS */);
+int mg_model_set_weights(mg_model *m, const float *w /* MG_MODEL_PARAMS */);
+void mg_model_destroy(mg_model *m);
+/* Features of roots (positions in time order; NULL = all n_edges roots) into
+ * feats (host, n x MG_NFEATURES): scaled log1p of the out/in degrees of both
+ * endpoints, of the entries of out(a), out(b), in(a), in(b) and of the whole
+ * edge list in the root's window (t, t + delta], the tree depth and the
+ * number of distinct motifs, and a constant 1 (all zero for self-loops). */
+int mg_root_features(const mg_graph *g, const mg_tree *tr, const int64_t *roots, int64_t n,
+                     float *feats);
+/* Forward pass on host features (n x MG_NFEATURES) -> out[n] (host). */
+int mg_model_predict(const mg_model *m, const float *feats, int64_t n, float *out);
+/* Adam (lr, betas 0.9/0.999) on mean squared error, minibatches of 32 in a
+ * seeded shuffled order; loss (optional, host) gets the mean loss per epoch. */
+int mg_model_train(mg_model *m, const float *feats, const float *labels, int64_t n,
+                   int32_t epochs, float lr, uint64_t seed, float *loss);
+
+/*
+ * Batches: many (graph, tree) jobs of uneven size counted by one persistent
+ * kernel launch.  The work queue holds root ranges ("items") of every job,
+ * largest graphs first; each step zeroes the counters with a fill kernel,
+ * runs the batched kernel and copies the counts back, and after the first
+ * step that sequence is replayed as one captured HIP graph.
+ *
+ *   graphs, trees : n jobs (the same graph may appear in several jobs); all
+ *                   graphs must live on the current device and use the same
+ *                   time width (mg_graph_info_t.time_bytes)
+ *   opts          : NULL = defaults (autotuned item size, graph replay)
+ * The handles must outlive the batch.  Counts are exact and independent of
+ * every option.
+ */
+typedef struct mg_batch mg_batch;  /* opaque */
+typedef struct {
+    int32_t blocks;           /* persistent workgroups; 0 = fill the device */
+    int32_t item_roots;       /* roots per work item (multiple of 64); 0 = autotune */
+    int32_t use_graph;        /* 1 = capture the step and replay it (default), 0 = plain launches */
+    int32_t reserved;
+    void *stream;             /* hipStream_t the steps run on (NULL = null stream) */
+} mg_batch_opts;
+void mg_batch_opts_init(mg_batch_opts *opts);
+int mg_batch_create(const mg_graph *const *graphs, const mg_tree *const *trees, int32_t n,
+                    const mg_batch_opts *opts, mg_batch **out);
+
+/* One step.  counts: host, sum of the trees' n_motifs, concatenated in job
+ * order, each tree in its caller's motif order.  elapsed_ms (optional): device
+ * time of the step from events on the batch's stream. */
+int mg_batch_count(mg_batch *b, uint64_t *counts, float *elapsed_ms);
+
+typedef struct {
+    int32_t n_jobs;
+    int32_t total_motifs;     /* length of the counts output */
+    int64_t total_roots;
+    int64_t n_items;
+    int32_t item_roots;       /* chosen (or given) item size */
+    int32_t blocks;           /* 0 = filled the device */
+    int32_t graph_captured;   /* 1 once a HIP graph replays the step */
+    int32_t depth;            /* deepest tree */
+    float tuned_ms;           /* best step time seen by the autotuner (0 if none) */
+} mg_batch_info_t;
+int mg_batch_info(const mg_batch *b, mg_batch_info_t *out);
+void mg_batch_destroy(mg_batch *b);
 
 /* Thread-local description of the last failure on this thread. */
 const char *mg_last_error(void);

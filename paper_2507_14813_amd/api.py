@@ -52,10 +52,26 @@ class CountOpts(ctypes.Structure):
                 ("stream", ctypes.c_void_p), ("roots", ctypes.c_void_p),
                 ("n_roots", ctypes.c_int64),
                 ("elapsed_ms", ctypes.POINTER(ctypes.c_float)),
-                ("stats", ctypes.c_void_p), ("root_cost", ctypes.c_void_p)]
+                ("stats", ctypes.c_void_p), ("sched", ctypes.c_int32),
+                ("reserved1", ctypes.c_int32), ("model", ctypes.c_void_p),
+                ("root_cost", ctypes.c_void_p)]
 
 
 STAT_NAMES = ("win_list", "win_all", "ent_list", "ent_all", "push", "credit", "roots")
+
+
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("blocks", ctypes.c_int32), ("item_roots", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("n_jobs", ctypes.c_int32), ("total_motifs", ctypes.c_int32),
+                ("total_roots", ctypes.c_int64), ("n_items", ctypes.c_int64),
+                ("item_roots", ctypes.c_int32), ("blocks", ctypes.c_int32),
+                ("graph_captured", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("tuned_ms", ctypes.c_float)]
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
@@ -103,8 +119,26 @@ def lib():
         L.mg_count_opts_init.restype = None
         L.mg_count.argtypes = [p, p, ctypes.POINTER(CountOpts), p]
         L.mg_last_error.restype = ctypes.c_char_p
+        L.mg_model_create.argtypes = [ctypes.c_uint64, ctypes.POINTER(p)]
+        L.mg_model_get_weights.argtypes = [p, p]
+        L.mg_model_set_weights.argtypes = [p, p]
+        L.mg_model_destroy.argtypes = [p]
+        L.mg_model_destroy.restype = None
+        L.mg_root_features.argtypes = [p, p, p, i64, p]
+        L.mg_model_predict.argtypes = [p, p, i64, p]
+        L.mg_model_train.argtypes = [p, p, p, i64, i32, ctypes.c_float, ctypes.c_uint64, p]
+        L.mg_batch_opts_init.argtypes = [ctypes.POINTER(BatchOpts)]
+        L.mg_batch_opts_init.restype = None
+        L.mg_batch_create.argtypes = [p, p, i32, ctypes.POINTER(BatchOpts), ctypes.POINTER(p)]
+        L.mg_batch_count.argtypes = [p, p, ctypes.POINTER(ctypes.c_float)]
+        L.mg_batch_info.argtypes = [p, ctypes.POINTER(BatchInfo)]
+        L.mg_batch_destroy.argtypes = [p]
+        L.mg_batch_destroy.restype = None
         for f in ("mg_set_allocator", "mg_graph_create", "mg_graph_info",
-                  "mg_tree_create", "mg_tree_info", "mg_count"):
+                  "mg_tree_create", "mg_tree_info", "mg_count", "mg_batch_create",
+                  "mg_batch_count", "mg_batch_info", "mg_model_create", "mg_model_get_weights",
+                  "mg_model_set_weights", "mg_root_features", "mg_model_predict",
+                  "mg_model_train"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -228,11 +262,12 @@ class Tree:
 
 
 def count(graph: Graph, tree: Tree, mode="comine", roots=None, blocks=0, chunk=0,
-          queues=0, stream=None, timed=False, stats=False, root_cost=False):
+          queues=0, stream=None, timed=False, stats=False, root_cost=False, model=None):
     """Exact count per motif (``mg_count``), in the tree's motif order.
 
     ``mode``: "comine" (one search over the MG-Tree) or "per_motif" (one search
-    per motif).  ``roots``: optional root positions (time order).  Returns a
+    per motif).  ``roots``: optional root positions (time order).  ``model``:
+    a ``Model`` selects the learned schedule.  Returns a
     uint64 array; with ``timed`` also the device milliseconds; with ``stats``
     also a dict of search statistics; with ``root_cost`` also the per-root
     cost log (uint64 per edge; both run instrumented kernels).
@@ -244,6 +279,9 @@ def count(graph: Graph, tree: Tree, mode="comine", roots=None, blocks=0, chunk=0
     o.blocks = int(blocks)
     o.chunk = int(chunk)
     o.queues = int(queues)
+    if model is not None:
+        o.sched = 1
+        o.model = model.handle.value
     o.stream = _default_stream(stream)
     r = None
     if roots is not None:
@@ -270,3 +308,115 @@ def count(graph: Graph, tree: Tree, mode="comine", roots=None, blocks=0, chunk=0
     if root_cost:
         res.append(rcost[:graph.n_edges])
     return res[0] if len(res) == 1 else tuple(res)
+
+
+NFEATURES = 16
+MODEL_PARAMS = 10497
+
+
+class Model:
+    """Root-cost MLP (``mg_model_*``): BF16 weights, FP32 accumulation."""
+
+    def __init__(self, seed=0, weights=None):
+        L = lib()
+        h = ctypes.c_void_p()
+        _check(L.mg_model_create(int(seed), ctypes.byref(h)))
+        self._h, self._L, self._done = h, L, _exiting
+        if weights is not None:
+            self.set_weights(weights)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def weights(self):
+        w = np.zeros(MODEL_PARAMS, dtype=np.float32)
+        _check(self._L.mg_model_get_weights(self._h, _p(w)))
+        return w
+
+    def set_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        assert w.size == MODEL_PARAMS
+        _check(self._L.mg_model_set_weights(self._h, _p(w)))
+
+    def predict(self, feats):
+        f = np.ascontiguousarray(feats, dtype=np.float32).reshape(-1, NFEATURES)
+        out = np.zeros(len(f), dtype=np.float32)
+        _check(self._L.mg_model_predict(self._h, _p(f), len(f), _p(out)))
+        return out
+
+    def train(self, feats, labels, epochs=5, lr=1e-3, seed=0):
+        f = np.ascontiguousarray(feats, dtype=np.float32).reshape(-1, NFEATURES)
+        y = np.ascontiguousarray(labels, dtype=np.float32)
+        assert len(y) == len(f)
+        loss = np.zeros(max(1, epochs), dtype=np.float32)
+        _check(self._L.mg_model_train(self._h, _p(f), _p(y), len(f), int(epochs), float(lr),
+                                      int(seed), _p(loss)))
+        return loss[:epochs]
+
+    def close(self):
+        if getattr(self, "_h", None) and not self._done():
+            self._L.mg_model_destroy(self._h)
+        self._h = None
+
+    __del__ = close
+
+
+def root_features(graph: Graph, tree: Tree, roots=None):
+    """Per-root features (n x 16) the cost model reads (``mg_root_features``)."""
+    L = lib()
+    if roots is None:
+        n, rp = graph.n_edges, None
+    else:
+        r = np.ascontiguousarray(roots, dtype=np.int64)
+        n, rp = len(r), (_p(r) if len(r) else _p(np.zeros(1, np.int64)))
+    out = np.zeros((max(1, n), NFEATURES), dtype=np.float32)
+    _check(L.mg_root_features(graph.handle, tree.handle, rp, n, _p(out)))
+    return out[:n]
+
+
+class Batch:
+    """Many (graph, tree) jobs counted by one persistent launch, replayed as a
+    captured HIP graph (``mg_batch_*``).  Keeps its graphs and trees alive."""
+
+    def __init__(self, graphs, trees, item_roots=0, blocks=0, use_graph=True, stream=None):
+        L = lib()
+        assert len(graphs) == len(trees) and len(graphs) > 0
+        self._graphs, self._trees = list(graphs), list(trees)
+        o = BatchOpts()
+        L.mg_batch_opts_init(ctypes.byref(o))
+        o.item_roots = int(item_roots)
+        o.blocks = int(blocks)
+        o.use_graph = 1 if use_graph else 0
+        o.stream = _default_stream(stream)
+        gh = (ctypes.c_void_p * len(graphs))(*[g.handle.value for g in graphs])
+        th = (ctypes.c_void_p * len(trees))(*[t.handle.value for t in trees])
+        h = ctypes.c_void_p()
+        _check(L.mg_batch_create(gh, th, len(graphs), ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._L = L
+        self._done = _exiting
+        self.sizes = [t.n_motifs for t in trees]
+
+    def info(self) -> dict:
+        bi = BatchInfo()
+        _check(self._L.mg_batch_info(self._h, ctypes.byref(bi)))
+        return {f: getattr(bi, f) for f, _ in BatchInfo._fields_}
+
+    def count(self, timed=False):
+        """Counts per job (list of uint64 arrays), plus device ms when timed."""
+        out = np.zeros(sum(self.sizes), dtype=np.uint64)
+        ms = ctypes.c_float(0.0)
+        _check(self._L.mg_batch_count(self._h, _p(out), ctypes.byref(ms) if timed else None))
+        parts, k = [], 0
+        for n in self.sizes:
+            parts.append(out[k:k + n])
+            k += n
+        return (parts, float(ms.value)) if timed else parts
+
+    def close(self):
+        if getattr(self, "_h", None) and not self._done():
+            self._L.mg_batch_destroy(self._h)
+        self._h = None
+
+    __del__ = close

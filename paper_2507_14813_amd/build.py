@@ -33,7 +33,7 @@ def _run(cmd):
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
     objs = []
-    for name in ("comine.hip",):
+    for name in ("comine.hip", "sched.hip"):
         obj = os.path.join(BUILD_DIR, name + ".o")
         out = _run([HIPCC, "-x", "hip", "--offload-arch=" + ARCH, *COMMON, *NO_PK_FP32,
                     "-c", os.path.join(CSRC, name), "-o", obj])

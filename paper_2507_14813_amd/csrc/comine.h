@@ -65,6 +65,8 @@ struct KParams {
     unsigned long long *stats;    // NULL, or kStats totals (zeroed before launch)
     unsigned long long *root_cost;  // NULL, or per root edge id: 1 + window entries
                                     // examined below that root (zeroed before launch)
+    const uint2 *items;           // NULL, or work items {first, end} of root positions
+    const uint32_t *n_items;      // device count of items (with items)
 };
 
 // search statistics (schedule independent), filled when KParams::stats is set
@@ -83,5 +85,34 @@ enum : int {
 // Returns a hipError_t value.
 template <typename TT>
 hipError_t launch_comine(const KParams<TT> &p, int blocks, hipStream_t stream);
+
+// ---- batches: many (graph, tree) jobs in one launch
+template <typename TT>
+struct BatchJob {
+    DevGraph<TT> g;
+    DevTree tree;
+    TT delta_sat;
+    uint32_t count_off;           // first counter of this job in BatchParams::counts
+};
+struct BatchItem {
+    uint32_t job, begin, end, pad;   // roots [begin, end) of one job
+};
+template <typename TT>
+struct BatchParams {
+    const BatchJob<TT> *jobs;
+    const BatchItem *items;
+    uint32_t n_items;
+    uint32_t n_q_max;             // largest tree's counter count
+    unsigned long long *cursor;   // item queue head, zeroed before launch
+    unsigned long long *counts;   // every job's counters, zeroed before launch
+};
+
+// `depth` = the deepest tree of the batch.
+template <typename TT>
+hipError_t launch_batch(const BatchParams<TT> &bp, int depth, int blocks, hipStream_t stream);
+
+// p[0..n) = v with a kernel (safe to record into a captured graph)
+hipError_t launch_fill_u64(unsigned long long *p, uint32_t n, unsigned long long v,
+                           hipStream_t stream);
 
 }  // namespace mg

@@ -33,88 +33,15 @@
 //     (1..5 motif edges), one instantiation per depth.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "comine.h"
+#include "device_util.h"
 
 namespace mg {
 namespace {
 
 constexpr uint32_t kChunkLimit = 0x7fffffffu;   // candidates per window chunk
-
-__device__ __forceinline__ void wave_sync() {
-    // Orders this wave's LDS accesses across lanes (LDS executes a wave's
-    // operations in order; the fences stop the compiler from moving them).
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ uint32_t uniform(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
-}
-
-__device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
-
-__device__ __forceinline__ uint32_t incl_scan32(uint32_t v, int lane) {
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        uint32_t o = __shfl_up(v, d);
-        if (lane >= d) v += o;
-    }
-    return v;
-}
-
-__device__ __forceinline__ uint64_t incl_scan64(uint64_t v, int lane) {
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        uint64_t o = __shfl_up(v, d);
-        if (lane >= d) v += o;
-    }
-    return v;
-}
-
-__device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t d) {
-    uint64_t s = (uint64_t)a + d;
-    return s > 0xffffffffull ? 0xffffffffu : (uint32_t)s;
-}
-__device__ __forceinline__ uint64_t sat_add(uint64_t a, uint64_t d) {
-    return a > ~0ull - d ? ~0ull : a + d;
-}
-
-// first index i in [lo, hi) with a[i << sh] > v (hi if none); sh = 1 walks
-// the time words of interleaved adjacency entries, sh = 0 a plain array
-template <typename TT>
-__device__ __forceinline__ uint32_t first_greater(const TT *__restrict__ a, uint32_t sh,
-                                                  uint32_t lo, uint32_t hi, TT v) {
-    uint32_t n = hi - lo;
-    while (n > 0) {
-        uint32_t h = n >> 1;
-        if (a[(size_t)(lo + h) << sh] <= v) { lo += h + 1; n -= h + 1; }
-        else n = h;
-    }
-    return lo;
-}
-
-// same, by exponential probing from lo (windows are short next to their lists)
-template <typename TT>
-__device__ __forceinline__ uint32_t gallop_greater(const TT *__restrict__ a, uint32_t sh,
-                                                   uint32_t lo, uint32_t hi, TT v) {
-    uint64_t step = 1;
-    for (;;) {
-        uint64_t probe = (uint64_t)lo + step - 1;
-        if (probe >= hi) return first_greater(a, sh, lo, hi, v);
-        if (a[(size_t)probe << sh] > v) return first_greater(a, sh, lo, (uint32_t)probe, v);
-        lo = (uint32_t)probe + 1;
-        step <<= 1;
-    }
-}
-
-template <typename TT>
-__device__ __forceinline__ const TT *times_of(const Entry<TT> *adj) {
-    return reinterpret_cast<const TT *>(adj) + 1;   // word 2i+1 is entry i's time
-}
 
 // child word of a group for scanned-endpoint index y (0..5 bound, else new)
 __device__ __forceinline__ uint32_t child_word(const uint4 &a, const uint4 &b, int y) {
@@ -394,6 +321,52 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
     }
 }
 
+// Search from roots [base, end) of the root list (positions, or edge ids when
+// p.roots is NULL), 64 at a time.
+template <typename TT, int D, int MODE>
+__device__ __forceinline__ void process_roots(const KParams<TT> &p,
+                                              WaveLds<TT, D, MODE == 2> &W,
+                                              unsigned long long *cnt, const int lane,
+                                              const uint32_t base, const uint32_t end,
+                                              Stats &st) {
+    constexpr bool STATS = MODE == 1, LOG = MODE == 2;
+    for (uint32_t b = base; b < end; b += kWave) {
+        const uint32_t i = b + (uint32_t)lane;
+        bool ok = i < end;
+        uint32_t r = 0;
+        int32_t s = 0, d = 0;
+        if (ok) {
+            r = p.roots ? p.roots[i] : i;
+            s = p.g.gsrc[r];
+            d = p.g.gdst[r];
+            ok = s != d;
+        }
+        const uint64_t m = __ballot(ok);
+        if (p.tree.root_q >= 0 && lane == 0 && m)
+            atomicAdd(&cnt[p.tree.root_q], (unsigned long long)__popcll(m));
+        if constexpr (STATS) st.v[kStatRoots] += ok ? 1 : 0;
+        if constexpr (LOG) {
+            if (ok) atomicAdd(&p.root_cost[r], 1ull);
+        }
+        if constexpr (D > 1) {
+            LevelBuf<TT, 1, LOG> &A = lvl<1>(W.lv);
+            if (ok) {
+                const uint32_t slot = mbcnt(m);
+                A.phi[0][slot] = s;
+                A.phi[1][slot] = d;
+                A.tfirst[slot] = p.g.gt[r];
+                if constexpr (LOG) A.root[slot] = r;
+            }
+            const uint32_t n1 = uniform((uint32_t)__popcll(m));
+            if (n1 > 0) {
+                wave_sync();
+                run_level<TT, D, MODE, 1>(p, W, cnt, lane, n1, st);
+                wave_sync();
+            }
+        }
+    }
+}
+
 template <typename TT, int D, int MODE>
 __global__ void __launch_bounds__(kWave * kWavesPerBlock)
 comine_kernel(const KParams<TT> p) {
@@ -412,10 +385,22 @@ comine_kernel(const KParams<TT> p) {
 #pragma unroll
     for (int i = 0; i < kStats; ++i) st.v[i] = 0;
 
+    if (p.items) {
+        // scheduled work items, claimed in order from one queue
+        const uint32_t n_items = uniform(*p.n_items);
+        for (;;) {
+            unsigned long long it = 0;
+            if (lane == 0) it = atomicAdd(&p.queues[0], 1ull);
+            it = __shfl(it, 0);
+            if (it >= n_items) break;
+            const uint2 item = p.items[uniform((uint32_t)it)];
+            process_roots<TT, D, MODE>(p, W, cnt, lane, uniform(item.x), uniform(item.y), st);
+        }
+    }
     // workgroups are dispatched to the XCDs round-robin: start on this XCD's
     // share of the roots, then take what is left of the others
-    const uint32_t nq = p.n_queues;
-    const uint32_t home = blockIdx.x % nq;
+    const uint32_t nq = p.items ? 0u : p.n_queues;
+    const uint32_t home = nq ? blockIdx.x % nq : 0u;
     for (uint32_t qi = 0; qi < nq; ++qi) {
         const uint32_t q = (home + qi) % nq;
         const uint32_t qbeg = (uint32_t)(((uint64_t)p.n_roots * q) / nq);
@@ -426,42 +411,7 @@ comine_kernel(const KParams<TT> p) {
             got = __shfl(got, 0);
             if (got >= (unsigned long long)(qend - qbeg)) break;
             const uint32_t base = uniform(qbeg + (uint32_t)got);
-            const uint32_t end = min(base + p.chunk, qend);
-            for (uint32_t b = base; b < end; b += kWave) {
-                const uint32_t i = b + (uint32_t)lane;
-                bool ok = i < end;
-                uint32_t r = 0;
-                int32_t s = 0, d = 0;
-                if (ok) {
-                    r = p.roots ? p.roots[i] : i;
-                    s = p.g.gsrc[r];
-                    d = p.g.gdst[r];
-                    ok = s != d;
-                }
-                const uint64_t m = __ballot(ok);
-                if (p.tree.root_q >= 0 && lane == 0 && m)
-                    atomicAdd(&cnt[p.tree.root_q], (unsigned long long)__popcll(m));
-                if constexpr (STATS) st.v[kStatRoots] += ok ? 1 : 0;
-                if constexpr (LOG) {
-                    if (ok) atomicAdd(&p.root_cost[r], 1ull);
-                }
-                if constexpr (D > 1) {
-                    LevelBuf<TT, 1, LOG> &A = lvl<1>(W.lv);
-                    if (ok) {
-                        const uint32_t slot = mbcnt(m);
-                        A.phi[0][slot] = s;
-                        A.phi[1][slot] = d;
-                        A.tfirst[slot] = p.g.gt[r];
-                        if constexpr (LOG) A.root[slot] = r;
-                    }
-                    const uint32_t n1 = uniform((uint32_t)__popcll(m));
-                    if (n1 > 0) {
-                        wave_sync();
-                        run_level<TT, D, MODE, 1>(p, W, cnt, lane, n1, st);
-                        wave_sync();
-                    }
-                }
-            }
+            process_roots<TT, D, MODE>(p, W, cnt, lane, base, min(base + p.chunk, qend), st);
         }
     }
 
@@ -473,6 +423,49 @@ comine_kernel(const KParams<TT> p) {
     __syncthreads();
     for (int i = (int)threadIdx.x; i < p.tree.n_q; i += (int)blockDim.x)
         if (cnt[i]) atomicAdd(&p.counts[i], cnt[i]);
+}
+
+// Many (graph, tree) jobs in one persistent launch.  Waves claim work items
+// (root ranges of one job) from one queue; each wave keeps its own LDS
+// counters, sized for the largest tree, and flushes them after every item.
+template <typename TT, int D>
+__global__ void __launch_bounds__(kWave * kWavesPerBlock)
+batch_kernel(const BatchParams<TT> bp) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const int wave = (int)(threadIdx.x / kWave);
+    const size_t cnt_bytes = ((size_t)bp.n_q_max * 8 + 15) & ~(size_t)15;
+    unsigned char *mine = smem + (size_t)wave * (cnt_bytes + sizeof(WaveLds<TT, D, false>));
+    unsigned long long *cnt = reinterpret_cast<unsigned long long *>(mine);
+    WaveLds<TT, D, false> &W = *reinterpret_cast<WaveLds<TT, D, false> *>(mine + cnt_bytes);
+    W.flag[lane] = 0;
+    Stats st;
+    for (;;) {
+        unsigned long long it = 0;
+        if (lane == 0) it = atomicAdd(bp.cursor, 1ull);
+        it = __shfl(it, 0);
+        if (it >= bp.n_items) break;
+        const BatchItem item = bp.items[uniform((uint32_t)it)];
+        const BatchJob<TT> &job = bp.jobs[uniform(item.job)];
+        KParams<TT> p{};
+        p.g = job.g;
+        p.tree = job.tree;
+        p.delta_sat = job.delta_sat;
+        p.roots = nullptr;
+        const uint32_t nq = (uint32_t)p.tree.n_q;
+        for (uint32_t i = (uint32_t)lane; i < nq; i += kWave) cnt[i] = 0;
+        wave_sync();
+        process_roots<TT, D, 0>(p, W, cnt, lane, uniform(item.begin), uniform(item.end), st);
+        wave_sync();
+        for (uint32_t i = (uint32_t)lane; i < nq; i += kWave)
+            if (cnt[i]) atomicAdd(&bp.counts[job.count_off + i], cnt[i]);
+        wave_sync();
+    }
+}
+
+__global__ void fill_u64(unsigned long long *p, uint32_t n, unsigned long long v) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        p[i] = v;
 }
 
 template <typename TT, int D, int MODE>
@@ -511,7 +504,51 @@ hipError_t launch_d(const KParams<TT> &p, int blocks, hipStream_t stream) {
     return launch_ds<TT, D, 0>(p, blocks, stream);
 }
 
+template <typename TT, int D>
+hipError_t launch_batch_d(const BatchParams<TT> &bp, int blocks, hipStream_t stream) {
+    const size_t sm = (size_t)kWavesPerBlock *
+                      ((((size_t)bp.n_q_max * 8 + 15) & ~(size_t)15) + sizeof(WaveLds<TT, D, false>));
+    auto kern = batch_kernel<TT, D>;
+    if (sm > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+        if (e != hipSuccess) return e;
+    }
+    if (blocks <= 0) {
+        int dev = 0, ncu = 0, per = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kWave * kWavesPerBlock, sm);
+        if (e != hipSuccess) return e;
+        blocks = ncu * (per > 0 ? per : 1);
+    }
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kWave * kWavesPerBlock), sm, stream, bp);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+template <typename TT>
+hipError_t launch_batch(const BatchParams<TT> &bp, int depth, int blocks, hipStream_t stream) {
+    switch (depth) {
+        case 1: return launch_batch_d<TT, 1>(bp, blocks, stream);
+        case 2: return launch_batch_d<TT, 2>(bp, blocks, stream);
+        case 3: return launch_batch_d<TT, 3>(bp, blocks, stream);
+        case 4: return launch_batch_d<TT, 4>(bp, blocks, stream);
+        case 5: return launch_batch_d<TT, 5>(bp, blocks, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, uint32_t n, unsigned long long v,
+                           hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    const uint32_t blocks = std::min<uint32_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(fill_u64, dim3(blocks), dim3(256), 0, stream, p, n, v);
+    return hipGetLastError();
+}
 
 template <typename TT>
 hipError_t launch_comine(const KParams<TT> &p, int blocks, hipStream_t stream) {
@@ -527,5 +564,7 @@ hipError_t launch_comine(const KParams<TT> &p, int blocks, hipStream_t stream) {
 
 template hipError_t launch_comine<uint32_t>(const KParams<uint32_t> &, int, hipStream_t);
 template hipError_t launch_comine<uint64_t>(const KParams<uint64_t> &, int, hipStream_t);
+template hipError_t launch_batch<uint32_t>(const BatchParams<uint32_t> &, int, int, hipStream_t);
+template hipError_t launch_batch<uint64_t>(const BatchParams<uint64_t> &, int, int, hipStream_t);
 
 }  // namespace mg

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -16,6 +17,7 @@
 
 #include "../../include/mayura.h"
 #include "comine.h"
+#include "sched.h"
 
 using mg::kVMax;
 using mg::kKMax;
@@ -366,6 +368,10 @@ int upload_tree(mg_tree *tr, int device, hipStream_t st) {
 
 // One launch of the co-mining kernel over a tree; counts land in d_counts.
 template <typename TT>
+int learned_search(const mg_graph *g, mg_tree *tr, const mg_model *model,
+                   const mg::KParams<TT> &base, int blocks, hipStream_t st);
+
+template <typename TT>
 int launch_tree(const mg_graph *g, mg_tree *tr, const uint32_t *d_roots, uint32_t n_roots,
                 unsigned long long *d_queues, unsigned long long *d_counts,
                 unsigned long long *d_stats, unsigned long long *d_cost,
@@ -406,7 +412,10 @@ int launch_tree(const mg_graph *g, mg_tree *tr, const uint32_t *d_roots, uint32_
         HIP_TRY(hipEventCreate(&e1));
         HIP_TRY(hipEventRecord(e0, st));
     }
-    if (n_roots > 0) {
+    if (n_roots > 0 && o.sched == MG_SCHED_LEARNED) {
+        int rc = learned_search<TT>(g, tr, o.model, p, o.blocks, st);
+        if (rc) return rc;
+    } else if (n_roots > 0) {
         hipError_t e = mg::launch_comine<TT>(p, o.blocks, st);
         if (e != hipSuccess)
             return fail(MG_EDEVICE, "co-mining launch failed: %s", hipGetErrorString(e));
@@ -418,6 +427,257 @@ int launch_tree(const mg_graph *g, mg_tree *tr, const uint32_t *d_roots, uint32_
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
     }
+    return MG_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- cost model
+static_assert(mg::kParams == MG_MODEL_PARAMS, "parameter layout");
+static_assert(mg::kFeat == MG_NFEATURES, "feature count");
+
+struct mg_model {
+    int device = 0;
+    DevBuf params, adam_m, adam_v;
+    ~mg_model() {
+        dev_free(params);
+        dev_free(adam_m);
+        dev_free(adam_v);
+    }
+};
+
+namespace {
+
+uint64_t splitmix(uint64_t &s) {
+    uint64_t z = (s += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+double uniform01(uint64_t &s) { return ((splitmix(s) >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
+double normal(uint64_t &s) {   // Box-Muller
+    const double u = uniform01(s), v = uniform01(s);
+    return std::sqrt(-2.0 * std::log(u)) * std::cos(6.283185307179586 * v);
+}
+
+template <typename TT>
+mg::DevGraph<TT> dev_graph(const mg_graph *g) {
+    mg::DevGraph<TT> d{};
+    d.gsrc = (const int32_t *)g->gsrc.ptr;
+    d.gdst = (const int32_t *)g->gdst.ptr;
+    d.gt = (const TT *)g->gt.ptr;
+    d.out_off = (const uint32_t *)g->out_off.ptr;
+    d.out_adj = (const mg::Entry<TT> *)g->out_adj.ptr;
+    d.in_off = (const uint32_t *)g->in_off.ptr;
+    d.in_adj = (const mg::Entry<TT> *)g->in_adj.ptr;
+    d.n_edges = (uint32_t)g->E;
+    return d;
+}
+
+mg::DevTree dev_tree(const mg_tree *tr) {
+    mg::DevTree t{};
+    t.inode = (const uint32_t *)tr->d_node.ptr;
+    t.grp = (const uint4 *)tr->d_grp.ptr;
+    t.n_q = (int32_t)tr->distinct.size();
+    t.root_q = tr->root_q;
+    t.depth = tr->depth;
+    return t;
+}
+
+template <typename TT>
+TT delta_sat(int64_t delta) {
+    return sizeof(TT) == 4 ? (TT)std::min<uint64_t>((uint64_t)delta, 0xffffffffull)
+                           : (TT)(uint64_t)delta;
+}
+
+// Learned schedule + search on stream st: predicted segment costs -> items ->
+// item-driven search kernel.
+template <typename TT>
+int learned_search(const mg_graph *g, mg_tree *tr, const mg_model *model,
+                   const mg::KParams<TT> &base, int blocks, hipStream_t st) {
+    const uint32_t E = (uint32_t)g->E;
+    const uint32_t n_seg = (E + mg::kSeg - 1) / mg::kSeg;
+    DevBuf d;
+    const size_t off_total = 4 * (size_t)n_seg;
+    const size_t off_work = off_total + 16;
+    const size_t off_nitems = off_work + 4 * (size_t)mg::kBinWords;
+    const size_t off_items = (off_nitems + 16 + 15) & ~(size_t)15;
+    int rc = dev_alloc(d, off_items + 8 * (size_t)std::max<uint32_t>(E, 1), (void *)st);
+    if (rc) return rc;
+    struct G { DevBuf *b; ~G() { dev_free(*b); } } guard{&d};
+    char *p0 = (char *)d.ptr;
+    float *seg_cost = (float *)p0, *total = (float *)(p0 + off_total);
+    uint32_t *work = (uint32_t *)(p0 + off_work), *n_items = (uint32_t *)(p0 + off_nitems);
+    uint2 *items = (uint2 *)(p0 + off_items);
+    hipError_t e = mg::launch_fill_f32_zero(total, 1, st);
+    if (e == hipSuccess)
+        e = mg::launch_predict_roots<TT>(base.g, base.tree, base.delta_sat,
+                                         (const float *)model->params.ptr, seg_cost, total, st);
+    // a segment worth more than ~1/(4 * resident waves) of the predicted total is split
+    if (e == hipSuccess)
+        e = mg::launch_bin(seg_cost, n_seg, E, total, 1.0f / 32768.0f, work, items, n_items, st);
+    if (e != hipSuccess) return fail(MG_EDEVICE, "learned schedule failed: %s", hipGetErrorString(e));
+    mg::KParams<TT> p = base;
+    p.items = items;
+    p.n_items = n_items;
+    p.roots = nullptr;
+    e = mg::launch_comine<TT>(p, blocks, st);
+    if (e != hipSuccess) return fail(MG_EDEVICE, "co-mining launch failed: %s", hipGetErrorString(e));
+    // the buffer is released after the caller synchronises the stream
+    HIP_TRY(hipStreamSynchronize(st));
+    return MG_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- batches
+struct mg_batch {
+    std::vector<const mg_graph *> graphs;
+    std::vector<mg_tree *> trees;
+    int time_bytes = 4;
+    int device = 0;
+    int depth = 1;
+    uint32_t n_q_max = 1;
+    uint32_t total_q = 0;         // device counters (distinct motifs per job)
+    int32_t total_motifs = 0;     // caller-visible counts
+    int64_t total_roots = 0;
+    std::vector<uint32_t> count_off;
+    mg_batch_opts opts{};
+    int32_t item_roots = 0;
+    float tuned_ms = 0.f;
+    std::vector<mg::BatchItem> items;
+    DevBuf d_jobs, d_items, d_work;   // d_work: cursor (16 B) + counters
+    uint64_t *h_counts = nullptr;     // pinned
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap_stream = nullptr;
+    ~mg_batch() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        if (h_counts) (void)hipHostFree(h_counts);
+        dev_free(d_jobs);
+        dev_free(d_items);
+        dev_free(d_work);
+    }
+};
+
+namespace {
+
+template <typename TT>
+int upload_jobs(mg_batch *b, hipStream_t st) {
+    std::vector<mg::BatchJob<TT>> jobs(b->graphs.size());
+    for (size_t j = 0; j < jobs.size(); ++j) {
+        const mg_graph *g = b->graphs[j];
+        mg_tree *tr = b->trees[j];
+        mg::BatchJob<TT> &J = jobs[j];
+        std::memset(&J, 0, sizeof J);
+        J.g.gsrc = (const int32_t *)g->gsrc.ptr;
+        J.g.gdst = (const int32_t *)g->gdst.ptr;
+        J.g.gt = (const TT *)g->gt.ptr;
+        J.g.out_off = (const uint32_t *)g->out_off.ptr;
+        J.g.out_adj = (const mg::Entry<TT> *)g->out_adj.ptr;
+        J.g.in_off = (const uint32_t *)g->in_off.ptr;
+        J.g.in_adj = (const mg::Entry<TT> *)g->in_adj.ptr;
+        J.g.n_edges = (uint32_t)g->E;
+        J.tree.inode = (const uint32_t *)tr->d_node.ptr;
+        J.tree.grp = (const uint4 *)tr->d_grp.ptr;
+        J.tree.n_q = (int32_t)tr->distinct.size();
+        J.tree.root_q = tr->root_q;
+        J.tree.depth = tr->depth;
+        J.delta_sat = sizeof(TT) == 4 ? (TT)std::min<uint64_t>((uint64_t)tr->delta, 0xffffffffull)
+                                      : (TT)(uint64_t)tr->delta;
+        J.count_off = b->count_off[j];
+    }
+    int rc = dev_alloc(b->d_jobs, sizeof(mg::BatchJob<TT>) * jobs.size(), (void *)st);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(b->d_jobs.ptr, jobs.data(), sizeof(mg::BatchJob<TT>) * jobs.size(),
+                           hipMemcpyHostToDevice, st));
+    return MG_OK;
+}
+
+// Work items: root ranges of item_roots roots, largest graphs first.
+int make_items(mg_batch *b, int32_t item_roots, hipStream_t st) {
+    std::vector<uint32_t> order(b->graphs.size());
+    std::iota(order.begin(), order.end(), 0u);
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+        return b->graphs[x]->E > b->graphs[y]->E;
+    });
+    b->items.clear();
+    for (uint32_t j : order) {
+        const uint32_t E = (uint32_t)b->graphs[j]->E;
+        for (uint32_t r = 0; r < E; r += (uint32_t)item_roots)
+            b->items.push_back({j, r, std::min<uint32_t>(E, r + (uint32_t)item_roots), 0u});
+    }
+    dev_free(b->d_items);
+    int rc = dev_alloc(b->d_items, sizeof(mg::BatchItem) * std::max<size_t>(1, b->items.size()),
+                       (void *)st);
+    if (rc) return rc;
+    if (!b->items.empty())
+        HIP_TRY(hipMemcpyAsync(b->d_items.ptr, b->items.data(),
+                               sizeof(mg::BatchItem) * b->items.size(), hipMemcpyHostToDevice, st));
+    b->item_roots = item_roots;
+    return MG_OK;
+}
+
+// Enqueue one step on st: zero, search, copy the counters to pinned memory.
+template <typename TT>
+int enqueue_step(mg_batch *b, hipStream_t st) {
+    mg::BatchParams<TT> bp{};
+    bp.jobs = (const mg::BatchJob<TT> *)b->d_jobs.ptr;
+    bp.items = (const mg::BatchItem *)b->d_items.ptr;
+    bp.n_items = (uint32_t)b->items.size();
+    bp.n_q_max = b->n_q_max;
+    bp.cursor = (unsigned long long *)b->d_work.ptr;
+    bp.counts = (unsigned long long *)((char *)b->d_work.ptr + 16);
+    hipError_t e = mg::launch_fill_u64(bp.cursor, 2 + b->total_q, 0ull, st);
+    if (e != hipSuccess) return fail(MG_EDEVICE, "fill launch failed: %s", hipGetErrorString(e));
+    if (bp.n_items) {
+        e = mg::launch_batch<TT>(bp, b->depth, b->opts.blocks, st);
+        if (e != hipSuccess) return fail(MG_EDEVICE, "batch launch failed: %s", hipGetErrorString(e));
+    }
+    HIP_TRY(hipMemcpyAsync(b->h_counts, bp.counts, 8 * (size_t)std::max<uint32_t>(1, b->total_q),
+                           hipMemcpyDeviceToHost, st));
+    return MG_OK;
+}
+
+int run_step(mg_batch *b, hipStream_t st, float *ms) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ms) {
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        HIP_TRY(hipEventRecord(e0, st));
+    }
+    int rc;
+    if (b->exec) {
+        HIP_TRY(hipGraphLaunch(b->exec, st));
+        rc = MG_OK;
+    } else {
+        rc = b->time_bytes == 4 ? enqueue_step<uint32_t>(b, st) : enqueue_step<uint64_t>(b, st);
+    }
+    if (rc) return rc;
+    if (ms) {
+        HIP_TRY(hipEventRecord(e1, st));
+        HIP_TRY(hipEventSynchronize(e1));
+        HIP_TRY(hipEventElapsedTime(ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    return MG_OK;
+}
+
+int capture(mg_batch *b) {
+    if (!b->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = b->time_bytes == 4 ? enqueue_step<uint32_t>(b, b->cap_stream)
+                                : enqueue_step<uint64_t>(b, b->cap_stream);
+    hipGraph_t gr = nullptr;
+    hipError_t e = hipStreamEndCapture(b->cap_stream, &gr);
+    if (rc) { if (gr) (void)hipGraphDestroy(gr); return rc; }
+    if (e != hipSuccess) return fail(MG_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    b->graph = gr;
+    HIP_TRY(hipGraphInstantiate(&b->exec, gr, nullptr, nullptr, 0));
     return MG_OK;
 }
 
@@ -436,6 +696,281 @@ int mg_set_allocator(mg_alloc_fn alloc, mg_release_fn release, void *ctx) {
 }
 
 const char *mg_last_error(void) { return g_err.c_str(); }
+
+int mg_model_create(uint64_t seed, mg_model **out) {
+    try {
+        if (!out) return fail(MG_EINVAL, "out is NULL");
+        std::unique_ptr<mg_model> m(new (std::nothrow) mg_model);
+        if (!m) return fail(MG_ENOMEM, "out of host memory");
+        HIP_TRY(hipGetDevice(&m->device));
+        std::vector<float> w(mg::kParams, 0.f);
+        uint64_t s = seed;
+        auto he = [&](int off, int fan_in, int rows, int cols) {
+            const double sd = std::sqrt(2.0 / fan_in);
+            for (int i = 0; i < rows * cols; ++i) w[off + i] = (float)(normal(s) * sd);
+        };
+        he(mg::kOffW1, mg::kFeat, mg::kFeat, mg::kHid);    // rows 16..31 stay zero
+        he(mg::kOffW2, mg::kHid, mg::kHid, mg::kHid);
+        he(mg::kOffW3, mg::kHid, mg::kHid, mg::kHid);
+        he(mg::kOffW4, mg::kHid, 1, mg::kHid);
+        for (DevBuf *b : {&m->params, &m->adam_m, &m->adam_v}) {
+            int rc = dev_alloc(*b, sizeof(float) * mg::kParams, nullptr);
+            if (rc) return rc;
+        }
+        HIP_TRY(hipMemcpy(m->params.ptr, w.data(), sizeof(float) * w.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemset(m->adam_m.ptr, 0, sizeof(float) * mg::kParams));
+        HIP_TRY(hipMemset(m->adam_v.ptr, 0, sizeof(float) * mg::kParams));
+        *out = m.release();
+        return MG_OK;
+    } catch (...) {
+        return fail(MG_EINTERNAL, "unexpected exception");
+    }
+}
+
+int mg_model_get_weights(const mg_model *m, float *w) {
+    if (!m || !w) return fail(MG_EINVAL, "NULL argument");
+    HIP_TRY(hipMemcpy(w, m->params.ptr, sizeof(float) * mg::kParams, hipMemcpyDeviceToHost));
+    return MG_OK;
+}
+
+int mg_model_set_weights(mg_model *m, const float *w) {
+    if (!m || !w) return fail(MG_EINVAL, "NULL argument");
+    for (int i = 0; i < mg::kParams; ++i)
+        if (!std::isfinite(w[i])) return fail(MG_EINVAL, "weight %d is not finite", i);
+    for (int r = mg::kFeat; r < 32; ++r)
+        for (int c = 0; c < mg::kHid; ++c)
+            if (w[mg::kOffW1 + r * mg::kHid + c] != 0.f)
+                return fail(MG_EINVAL, "W1 rows %d..31 must be zero", mg::kFeat);
+    HIP_TRY(hipMemcpy(m->params.ptr, w, sizeof(float) * mg::kParams, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(m->adam_m.ptr, 0, sizeof(float) * mg::kParams));
+    HIP_TRY(hipMemset(m->adam_v.ptr, 0, sizeof(float) * mg::kParams));
+    return MG_OK;
+}
+
+void mg_model_destroy(mg_model *m) { delete m; }
+
+int mg_root_features(const mg_graph *g, const mg_tree *tr_c, const int64_t *roots, int64_t n,
+                     float *feats) {
+    try {
+        if (!g || !tr_c || !feats || n < 0) return fail(MG_EINVAL, "bad argument");
+        if (!roots && n != g->E) return fail(MG_EINVAL, "without roots, n must be n_edges");
+        mg_tree *tr = const_cast<mg_tree *>(tr_c);
+        int rc = upload_tree(tr, g->device, nullptr);
+        if (rc) return rc;
+        std::vector<uint32_t> r;
+        if (roots) {
+            r.resize(n);
+            for (int64_t i = 0; i < n; ++i) {
+                if (roots[i] < 0 || roots[i] >= g->E) return fail(MG_EINVAL, "root out of range");
+                r[i] = (uint32_t)roots[i];
+            }
+        }
+        DevBuf d_r, d_f;
+        struct G { DevBuf *a, *b; ~G() { dev_free(*a); dev_free(*b); } } guard{&d_r, &d_f};
+        if (roots) {
+            rc = dev_alloc(d_r, 4 * std::max<size_t>(1, r.size()), nullptr);
+            if (rc) return rc;
+            if (n) HIP_TRY(hipMemcpy(d_r.ptr, r.data(), 4 * r.size(), hipMemcpyHostToDevice));
+        }
+        rc = dev_alloc(d_f, sizeof(float) * mg::kFeat * std::max<int64_t>(1, n), nullptr);
+        if (rc) return rc;
+        hipError_t e = g->time_bytes == 4
+            ? mg::launch_features<uint32_t>(dev_graph<uint32_t>(g), dev_tree(tr),
+                                            delta_sat<uint32_t>(tr->delta),
+                                            (const uint32_t *)d_r.ptr, (uint32_t)n,
+                                            (float *)d_f.ptr, nullptr)
+            : mg::launch_features<uint64_t>(dev_graph<uint64_t>(g), dev_tree(tr),
+                                            delta_sat<uint64_t>(tr->delta),
+                                            (const uint32_t *)d_r.ptr, (uint32_t)n,
+                                            (float *)d_f.ptr, nullptr);
+        if (e != hipSuccess) return fail(MG_EDEVICE, "features launch failed: %s", hipGetErrorString(e));
+        if (n) HIP_TRY(hipMemcpy(feats, d_f.ptr, sizeof(float) * mg::kFeat * n, hipMemcpyDeviceToHost));
+        return MG_OK;
+    } catch (...) {
+        return fail(MG_EINTERNAL, "unexpected exception");
+    }
+}
+
+int mg_model_predict(const mg_model *m, const float *feats, int64_t n, float *out) {
+    try {
+        if (!m || !feats || !out || n < 0 || n >= (int64_t)1 << 31)
+            return fail(MG_EINVAL, "bad argument");
+        DevBuf d_f, d_o;
+        struct G { DevBuf *a, *b; ~G() { dev_free(*a); dev_free(*b); } } guard{&d_f, &d_o};
+        int rc = dev_alloc(d_f, sizeof(float) * mg::kFeat * std::max<int64_t>(1, n), nullptr);
+        if (rc) return rc;
+        rc = dev_alloc(d_o, sizeof(float) * std::max<int64_t>(1, n), nullptr);
+        if (rc) return rc;
+        if (n) HIP_TRY(hipMemcpy(d_f.ptr, feats, sizeof(float) * mg::kFeat * n, hipMemcpyHostToDevice));
+        hipError_t e = mg::launch_predict_feats((const float *)m->params.ptr, (const float *)d_f.ptr,
+                                                (uint32_t)n, (float *)d_o.ptr, nullptr);
+        if (e != hipSuccess) return fail(MG_EDEVICE, "predict launch failed: %s", hipGetErrorString(e));
+        if (n) HIP_TRY(hipMemcpy(out, d_o.ptr, sizeof(float) * n, hipMemcpyDeviceToHost));
+        return MG_OK;
+    } catch (...) {
+        return fail(MG_EINTERNAL, "unexpected exception");
+    }
+}
+
+int mg_model_train(mg_model *m, const float *feats, const float *labels, int64_t n,
+                   int32_t epochs, float lr, uint64_t seed, float *loss) {
+    try {
+        if (!m || !feats || !labels || n < 0 || n >= (int64_t)1 << 31 || epochs < 0 ||
+            !(lr > 0.f))
+            return fail(MG_EINVAL, "bad argument");
+        std::vector<uint32_t> perm(n);
+        std::iota(perm.begin(), perm.end(), 0u);
+        uint64_t s = seed;
+        for (int64_t i = n - 1; i > 0; --i) std::swap(perm[i], perm[splitmix(s) % (uint64_t)(i + 1)]);
+        DevBuf d_f, d_y, d_p, d_l;
+        struct G {
+            DevBuf *a, *b, *c, *d;
+            ~G() { dev_free(*a); dev_free(*b); dev_free(*c); dev_free(*d); }
+        } guard{&d_f, &d_y, &d_p, &d_l};
+        int rc = dev_alloc(d_f, sizeof(float) * mg::kFeat * std::max<int64_t>(1, n), nullptr);
+        if (!rc) rc = dev_alloc(d_y, sizeof(float) * std::max<int64_t>(1, n), nullptr);
+        if (!rc) rc = dev_alloc(d_p, sizeof(uint32_t) * std::max<int64_t>(1, n), nullptr);
+        if (!rc) rc = dev_alloc(d_l, sizeof(float) * std::max(1, epochs), nullptr);
+        if (rc) return rc;
+        if (n) {
+            HIP_TRY(hipMemcpy(d_f.ptr, feats, sizeof(float) * mg::kFeat * n, hipMemcpyHostToDevice));
+            HIP_TRY(hipMemcpy(d_y.ptr, labels, sizeof(float) * n, hipMemcpyHostToDevice));
+            HIP_TRY(hipMemcpy(d_p.ptr, perm.data(), sizeof(uint32_t) * n, hipMemcpyHostToDevice));
+        }
+        hipError_t e = mg::launch_train((float *)m->params.ptr, (float *)m->adam_m.ptr,
+                                        (float *)m->adam_v.ptr, (const float *)d_f.ptr,
+                                        (const float *)d_y.ptr, (uint32_t)n,
+                                        (const uint32_t *)d_p.ptr, (uint32_t)epochs, lr,
+                                        (float *)d_l.ptr, nullptr);
+        if (e != hipSuccess) return fail(MG_EDEVICE, "train launch failed: %s", hipGetErrorString(e));
+        HIP_TRY(hipDeviceSynchronize());
+        if (loss && epochs)
+            HIP_TRY(hipMemcpy(loss, d_l.ptr, sizeof(float) * epochs, hipMemcpyDeviceToHost));
+        return MG_OK;
+    } catch (...) {
+        return fail(MG_EINTERNAL, "unexpected exception");
+    }
+}
+
+void mg_batch_opts_init(mg_batch_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->use_graph = 1;
+}
+
+int mg_batch_create(const mg_graph *const *graphs, const mg_tree *const *trees, int32_t n,
+                    const mg_batch_opts *opts, mg_batch **out) {
+    try {
+        if (!out || !graphs || !trees || n < 1) return fail(MG_EINVAL, "empty batch");
+        mg_batch_opts o;
+        mg_batch_opts_init(&o);
+        if (opts) o = *opts;
+        if (o.item_roots < 0 || o.item_roots % 64 || o.item_roots > (1 << 24))
+            return fail(MG_EINVAL, "item_roots must be a multiple of 64 in [0, 2^24]");
+        int dev = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        std::unique_ptr<mg_batch> b(new (std::nothrow) mg_batch);
+        if (!b) return fail(MG_ENOMEM, "out of host memory");
+        b->opts = o;
+        b->device = dev;
+        hipStream_t st = (hipStream_t)o.stream;
+        for (int32_t j = 0; j < n; ++j) {
+            if (!graphs[j] || !trees[j]) return fail(MG_EINVAL, "job %d has a NULL handle", j);
+            if (graphs[j]->device != dev) return fail(MG_EINVAL, "job %d: graph on another device", j);
+            if (j && graphs[j]->time_bytes != graphs[0]->time_bytes)
+                return fail(MG_EUNSUPPORTED, "graphs of one batch must share the time width");
+            mg_tree *tr = const_cast<mg_tree *>(trees[j]);
+            int rc = upload_tree(tr, dev, st);
+            if (rc) return rc;
+            b->graphs.push_back(graphs[j]);
+            b->trees.push_back(tr);
+            b->count_off.push_back(b->total_q);
+            b->total_q += (uint32_t)tr->distinct.size();
+            b->total_motifs += tr->n_motifs;
+            b->total_roots += graphs[j]->E;
+            b->n_q_max = std::max<uint32_t>(b->n_q_max, (uint32_t)tr->distinct.size());
+            b->depth = std::max(b->depth, tr->depth);
+        }
+        b->time_bytes = graphs[0]->time_bytes;
+        int rc = b->time_bytes == 4 ? upload_jobs<uint32_t>(b.get(), st)
+                                    : upload_jobs<uint64_t>(b.get(), st);
+        if (rc) return rc;
+        rc = dev_alloc(b->d_work, 16 + 8 * (size_t)std::max<uint32_t>(1, b->total_q), (void *)st);
+        if (rc) return rc;
+        HIP_TRY(hipHostMalloc((void **)&b->h_counts, 8 * (size_t)std::max<uint32_t>(1, b->total_q),
+                              hipHostMallocDefault));
+        if (o.item_roots > 0) {
+            rc = make_items(b.get(), o.item_roots, st);
+            if (rc) return rc;
+        } else {
+            // autotune the item size: time one step per candidate, keep the best
+            float best = -1.f;
+            int32_t best_ir = 64;
+            for (int32_t ir : {64, 128, 256, 512, 2048}) {
+                rc = make_items(b.get(), ir, st);
+                if (rc) return rc;
+                float ms = 0.f;
+                rc = run_step(b.get(), st, nullptr);   // warm
+                if (rc) return rc;
+                rc = run_step(b.get(), st, &ms);
+                if (rc) return rc;
+                if (best < 0.f || ms < best) { best = ms; best_ir = ir; }
+            }
+            b->tuned_ms = best;
+            rc = make_items(b.get(), best_ir, st);
+            if (rc) return rc;
+        }
+        HIP_TRY(hipStreamSynchronize(st));
+        *out = b.release();
+        return MG_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(MG_ENOMEM, "out of host memory");
+    } catch (...) {
+        return fail(MG_EINTERNAL, "unexpected exception");
+    }
+}
+
+int mg_batch_count(mg_batch *b, uint64_t *counts, float *elapsed_ms) {
+    try {
+        if (!b || !counts) return fail(MG_EINVAL, "NULL argument");
+        int dev = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        if (dev != b->device) return fail(MG_EINVAL, "batch lives on device %d", b->device);
+        hipStream_t st = (hipStream_t)b->opts.stream;
+        int rc;
+        if (b->opts.use_graph && !b->exec) {
+            rc = capture(b);
+            if (rc) return rc;
+        }
+        rc = run_step(b, st, elapsed_ms);
+        if (rc) return rc;
+        int32_t k = 0;
+        for (size_t j = 0; j < b->trees.size(); ++j) {
+            const mg_tree *tr = b->trees[j];
+            for (int32_t i = 0; i < tr->n_motifs; ++i)
+                counts[k++] = b->h_counts[b->count_off[j] + tr->motif_q[i]];
+        }
+        return MG_OK;
+    } catch (...) {
+        return fail(MG_EINTERNAL, "unexpected exception");
+    }
+}
+
+int mg_batch_info(const mg_batch *b, mg_batch_info_t *out) {
+    if (!b || !out) return fail(MG_EINVAL, "NULL argument");
+    out->n_jobs = (int32_t)b->trees.size();
+    out->total_motifs = b->total_motifs;
+    out->total_roots = b->total_roots;
+    out->n_items = (int64_t)b->items.size();
+    out->item_roots = b->item_roots;
+    out->blocks = b->opts.blocks;
+    out->graph_captured = b->exec ? 1 : 0;
+    out->depth = b->depth;
+    out->tuned_ms = b->tuned_ms;
+    return MG_OK;
+}
+
+void mg_batch_destroy(mg_batch *b) { delete b; }
 
 int mg_graph_create(const int32_t *src, const int32_t *dst, const int64_t *t, int64_t n_edges,
                     int32_t n_nodes, uint32_t flags, void *stream, mg_graph **out) {
@@ -564,6 +1099,13 @@ int mg_count(const mg_graph *g, const mg_tree *tr_c, const mg_count_opts *opts,
             return fail(MG_EINVAL, "queues must be in [0, %d]", mg::kQueues);
         if (o.stats && o.root_cost)
             return fail(MG_EINVAL, "stats and root_cost are exclusive");
+        if (o.sched != MG_SCHED_PLAIN && o.sched != MG_SCHED_LEARNED)
+            return fail(MG_EINVAL, "unknown schedule %d", o.sched);
+        if (o.sched == MG_SCHED_LEARNED) {
+            if (!o.model) return fail(MG_EINVAL, "the learned schedule needs a model");
+            if (o.roots) return fail(MG_EINVAL, "the learned schedule searches every root");
+            if (o.model->device != g->device) return fail(MG_EINVAL, "model on another device");
+        }
         int dev = 0;
         HIP_TRY(hipGetDevice(&dev));
         if (dev != g->device) return fail(MG_EINVAL, "graph lives on device %d, current is %d",

@@ -1,0 +1,65 @@
+// Learned root-cost scheduler: features, MLP (BF16 weights, FP32
+// accumulation on MFMA), training, and cost binning.  Internal interface
+// between host.cpp and sched.hip.
+#pragma once
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#include "comine.h"
+
+namespace mg {
+
+constexpr int kFeat = 16;       // features per root (padded to 32 for MFMA)
+constexpr int kHid = 64;        // hidden width
+constexpr int kSeg = 64;        // roots per scheduling segment
+
+// Parameter vector (fp32 master copy), row-major [in][out]:
+//   W1 [32][64] (rows 16..31 stay zero), b1[64], W2[64][64], b2[64],
+//   W3[64][64], b3[64], W4[64], b4[1]
+constexpr int kOffW1 = 0;
+constexpr int kOffB1 = kOffW1 + 32 * kHid;
+constexpr int kOffW2 = kOffB1 + kHid;
+constexpr int kOffB2 = kOffW2 + kHid * kHid;
+constexpr int kOffW3 = kOffB2 + kHid;
+constexpr int kOffB3 = kOffW3 + kHid * kHid;
+constexpr int kOffW4 = kOffB3 + kHid;
+constexpr int kOffB4 = kOffW4 + kHid;
+constexpr int kParams = kOffB4 + 1;
+
+// Features of the roots [0, n) of `roots` (or edge ids 0..n-1), fp32 n x 16.
+template <typename TT>
+hipError_t launch_features(const DevGraph<TT> &g, const DevTree &t, TT delta_sat,
+                           const uint32_t *roots, uint32_t n, float *feats, hipStream_t st);
+
+// MLP forward on given fp32 features (n x 16) -> predicted log-cost.
+hipError_t launch_predict_feats(const float *params, const float *feats, uint32_t n, float *out,
+                                hipStream_t st);
+
+// Fused: features + MLP for every root edge; per 64-root segment writes the
+// sum of exp(prediction) (predicted cost) to seg_cost[n_edges / 64 rounded up]
+// and adds every segment to *total (zeroed by the caller).
+template <typename TT>
+hipError_t launch_predict_roots(const DevGraph<TT> &g, const DevTree &t, TT delta_sat,
+                                const float *params, float *seg_cost, float *total,
+                                hipStream_t st);
+
+// Binning: from segment costs, write work items {begin, end} (root ranges),
+// heaviest cost bin first; a segment costlier than split_frac * (*total)
+// becomes one item per root.  work: scratch of kBinWords u32 (zeroed here);
+// items: capacity n_roots; n_items_out: device u32.
+constexpr int kBins = 48;
+constexpr int kBinWords = 3 * kBins + 4;
+hipError_t launch_bin(const float *seg_cost, uint32_t n_seg, uint32_t n_roots, const float *total,
+                      float split_frac, uint32_t *work, uint2 *items, uint32_t *n_items_out,
+                      hipStream_t st);
+
+// p[0..n) = 0 with a kernel
+hipError_t launch_fill_f32_zero(float *p, uint32_t n, hipStream_t st);
+
+// Train on (features, label) pairs with Adam; one wave, minibatches of 32.
+// params, adam_m, adam_v: kParams fp32 each (device).  loss: per epoch (device).
+hipError_t launch_train(float *params, float *adam_m, float *adam_v, const float *feats,
+                        const float *labels, uint32_t n, const uint32_t *perm, uint32_t epochs,
+                        float lr, float *loss, hipStream_t st);
+
+}  // namespace mg

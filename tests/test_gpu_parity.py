@@ -221,6 +221,47 @@ def test_per_root_cost_log_matches_oracle():
         assert (cpm >= cost).all() and cpm.sum() > cost.sum()
 
 
+def test_batch_equals_single_counts_and_oracle(gpu):
+    """Jobs of uneven size and depth (one graph shared by two jobs) in one
+    launch; every replay of the captured step matches the single counts and
+    the oracle, with eager work between replays."""
+    rng = np.random.default_rng(12)
+    graphs, trees, want = [], [], []
+    for j in range(7):
+        E = int(rng.integers(50, 3000))
+        n = int(rng.integers(5, 60))
+        s, d, t = tiny_graph(rng, n, E, int(rng.integers(50, 2000)), self_loops=True)
+        ms = W.random_extension_motifs(int(rng.integers(2, 12)), (1, 2, 3, 4), 5, 50 + j)
+        delta = int(rng.integers(0, 200))
+        og = OracleGraph(s, d, t, n)
+        g = api.Graph(s, d, t, n)
+        graphs.append(g)
+        trees.append(api.Tree(ms, delta))
+        want.append(oracle_counts(og, ms, delta))
+        if j == 2:   # same graph, second motif group
+            ms2 = [[(0, 1), (1, 0)], [(0, 1), (1, 2), (2, 0)], [(5, 6)]]
+            graphs.append(g)
+            trees.append(api.Tree(ms2, delta + 7))
+            want.append(oracle_counts(og, ms2, delta + 7))
+    single = [api.count(g, tr) for g, tr in zip(graphs, trees)]
+    for a, b in zip(single, want):
+        assert np.array_equal(a, b)
+    for kw in (dict(), dict(item_roots=64), dict(item_roots=192, use_graph=False)):
+        say("batch", kw)
+        b = api.Batch(graphs, trees, **kw)
+        for rep in range(3):
+            got = b.count()
+            for a, w in zip(got, want):
+                assert np.array_equal(a, w), (kw, rep)
+            x = gpu.arange(1000, device="cuda").sum()      # eager work between replays
+            gpu.cuda.synchronize()
+            assert int(x) == 499500
+        info = b.info()
+        assert info["graph_captured"] == (0 if kw.get("use_graph") is False else 1)
+        assert info["n_jobs"] == len(graphs) and info["item_roots"] % 64 == 0
+        b.close()
+
+
 def test_config1_full():
     wl = W.make_config(1)
     s, d, t, n = wl.graphs[0]
