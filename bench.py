@@ -58,6 +58,205 @@ def cpu_baseline(s, d, t, n, motifs, delta, target_s):
                       "one oracle pass per motif (%.1f s)" % (n_s, len(motifs), dt)}
 
 
+def timed_steps(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = None
+    for _ in range(steps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, out
+
+
+def bench_batched(args):
+    """64 graphs of uneven size with their own motif sets: one persistent,
+    graph-captured launch vs 64 sequential launches vs per-motif launches."""
+    import numpy as np
+    import torch
+    from paper_2507_14813_amd import api, workloads as W
+    wl = W.make_config(3, scale=args.scale)
+    graphs = [api.Graph(s, d, t, n, sorted_by_t=True) for (s, d, t, n) in wl.graphs]
+    trees = [api.Tree(ms, dl) for ms, dl in zip(wl.motif_sets, wl.deltas)]
+    E = sum(len(g[0]) for g in wl.graphs)
+    ref = [api.count(g, tr) for g, tr in zip(graphs, trees)]
+    t0 = time.perf_counter()
+    b = api.Batch(graphs, trees)
+    create_s = time.perf_counter() - t0
+    # cost model trained on root costs of other graphs from the same recipe
+    rng = np.random.default_rng(9)
+    feats, labels = [], []
+    for k in range(6):
+        Et = int(rng.integers(100_000, 600_000))
+        st, dt, tt = W.powerlaw_graph(Et // 10, Et, float(rng.uniform(1.9, 2.5)), 30_000_000,
+                                      seed=9000 + k, burst_cap=64)
+        gt = api.Graph(st, dt, tt, Et // 10, sorted_by_t=True)
+        trt = api.Tree(W.random_extension_motifs(int(rng.integers(4, 25)), (2, 3, 4), 5, 9000 + k),
+                       int(rng.choice([600, 3600, 86400])))
+        _, cost = api.count(gt, trt, root_cost=True)
+        f = api.root_features(gt, trt)
+        live = np.flatnonzero(cost > 0)
+        pick = rng.choice(live, min(len(live), 40_000), replace=False)
+        feats.append(f[pick])
+        labels.append(np.log1p(cost[pick]).astype(np.float32))
+    model = api.Model(seed=1)
+    loss = model.train(np.concatenate(feats), np.concatenate(labels), epochs=args.train_epochs,
+                       lr=2e-3, seed=3)
+    log("batch model loss", np.round(loss, 3))
+    t0 = time.perf_counter()
+    bl = api.Batch(graphs, trees, model=model)
+    create_learned_s = time.perf_counter() - t0
+
+    def batched():
+        out = b.count()
+        return out
+
+    def sequential(mode="comine"):
+        return [api.count(g, tr, mode=mode) for g, tr in zip(graphs, trees)]
+
+    tb, out = timed_steps(batched, args.steps, args.warmup)
+    assert all(np.array_equal(a, r) for a, r in zip(out, ref))
+    tbl, out = timed_steps(bl.count, args.steps, args.warmup)
+    assert all(np.array_equal(a, r) for a, r in zip(out, ref))
+    ts, out = timed_steps(sequential, args.steps, args.warmup)
+    assert all(np.array_equal(a, r) for a, r in zip(out, ref))
+    tp, out = timed_steps(lambda: sequential("per_motif"), 1, 0)
+    assert all(np.array_equal(a, r) for a, r in zip(out, ref))
+    info = b.info()
+    return {
+        "metric": "root edges searched/s, learned + batched (64 graphs, one captured launch), "
+                  "exact counts",
+        "value": E / tbl, "unit": "root edges/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * tbl, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32/u32, u64 counts",
+        "data": "synthetic",
+        "config": {"workload": "64 powerlaw graphs, E log-uniform 1e4-2e6 (sum %d), "
+                               "4-24 motifs of 2-4 edges each" % E,
+                   "n_motifs": int(sum(len(m) for m in wl.motif_sets))},
+        "batched_plain_ms": 1e3 * tb, "sequential_ms": 1e3 * ts, "per_motif_ms": 1e3 * tp,
+        "speedup_vs_batched_plain": tb / tbl, "speedup_vs_sequential": ts / tbl,
+        "speedup_vs_per_motif": tp / tbl,
+        "batch": info, "batch_create_s": create_s, "learned_batch_create_s": create_learned_s,
+        "train_loss": [float(x) for x in loss],
+    }
+
+
+def bench_learned(args):
+    """Config 4: the learned schedule vs the plain one vs per-motif mining.
+    The model is trained on root costs logged on a separately seeded graph."""
+    import numpy as np
+    import torch
+    from paper_2507_14813_amd import api, workloads as W
+    wl = W.make_config(4, scale=args.scale)
+    s, d, t, n = wl.graphs[0]
+    ms, delta = wl.motif_sets[0], wl.deltas[0]
+    E = len(s)
+    g = api.Graph(s, d, t, n, sorted_by_t=True)
+    tr = api.Tree(ms, delta)
+    # training data: same recipe, another seed, a fifth of the size
+    V2, E2 = max(16, n // 5), max(16, E // 5)
+    s2, d2, t2 = W.powerlaw_graph(V2, E2, 1.8, 30_000_000, seed=104, burst_cap=64)
+    g2 = api.Graph(s2, d2, t2, V2, sorted_by_t=True)
+    t0 = time.perf_counter()
+    _, cost2 = api.count(g2, tr, root_cost=True)
+    f2 = api.root_features(g2, tr)
+    live = np.flatnonzero(cost2 > 0)
+    rng = np.random.default_rng(0)
+    pick = rng.choice(live, min(len(live), args.train_samples), replace=False)
+    model = api.Model(seed=1)
+    loss = model.train(f2[pick], np.log1p(cost2[pick]).astype(np.float32),
+                       epochs=args.train_epochs, lr=2e-3, seed=2)
+    train_s = time.perf_counter() - t0
+    log("trained on %d roots in %.1f s, loss %s" % (len(pick), train_s, np.round(loss, 3)))
+    # held-out quality on the benchmark graph itself
+    ref, cost = api.count(g, tr, root_cost=True)
+    fe = api.root_features(g, tr)
+    lv = cost > 0
+    pred = model.predict(fe[lv])
+    rank = lambda x: np.argsort(np.argsort(x))
+    rho = float(np.corrcoef(rank(pred), rank(np.log1p(cost[lv])))[0, 1])
+    tp_, _ = timed_steps(lambda: api.count(g, tr), args.steps, args.warmup)
+    tl_, c = timed_steps(lambda: api.count(g, tr, model=model), args.steps, args.warmup)
+    assert np.array_equal(c, ref)
+    out = {
+        "metric": "root edges searched/s, learned schedule (config 4), exact counts",
+        "value": E / tl_, "unit": "root edges/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * tl_, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32/u32, u64 counts; MLP bf16/fp32",
+        "data": "synthetic",
+        "config": {"workload": "powerlaw V=%d E=%d gamma=1.8 delta=%d, 756 motifs "
+                               "(3- and 4-edge, <=4 nodes)" % (n, E, delta)},
+        "plain_ms": 1e3 * tp_, "speedup_vs_plain": tp_ / tl_,
+        "held_out_spearman": rho, "train_loss": [float(x) for x in loss], "train_s": train_s,
+    }
+    if args.per_motif_steps:
+        tpm, c = timed_steps(lambda: api.count(g, tr, mode="per_motif"), 1, 0)
+        assert np.array_equal(c, ref)
+        out["per_motif_ms"] = 1e3 * tpm
+        out["speedup_vs_per_motif"] = tpm / tl_
+    return out
+
+
+def bench_sweep(args):
+    """Config 5: one 200M-edge graph, 48 motifs of 3-5 edges, delta swept over
+    {900, 3600, 21600}: the three trees in one learned + batched launch vs
+    three plain launches vs per-motif mining."""
+    import numpy as np
+    import torch
+    from paper_2507_14813_amd import api, workloads as W
+    t0 = time.perf_counter()
+    wl = W.make_config(5, scale=args.scale)
+    s, d, t, n = wl.graphs[0]
+    ms = wl.motif_sets[0]
+    E = len(s)
+    log("generated %d edges in %.1f s" % (E, time.perf_counter() - t0))
+    g = api.Graph(s, d, t, n, sorted_by_t=True)
+    del s, d, t
+    trees = [api.Tree(ms, dl) for dl in wl.deltas]
+    ref = [api.count(g, tr) for tr in trees]
+    # model trained on a separately seeded graph of the same recipe, a tenth of the size
+    V2, E2 = max(16, n // 10), max(16, E // 10)
+    s2, d2, t2 = W.powerlaw_graph(V2, E2, 2.0, 100_000_000, seed=105, burst_cap=32)
+    g2 = api.Graph(s2, d2, t2, V2, sorted_by_t=True)
+    rng = np.random.default_rng(0)
+    feats, labels = [], []
+    for tr in trees:
+        _, cost = api.count(g2, tr, root_cost=True)
+        f = api.root_features(g2, tr)
+        live = np.flatnonzero(cost > 0)
+        pick = rng.choice(live, min(len(live), args.train_samples // 3), replace=False)
+        feats.append(f[pick])
+        labels.append(np.log1p(cost[pick]).astype(np.float32))
+    model = api.Model(seed=1)
+    loss = model.train(np.concatenate(feats), np.concatenate(labels), epochs=args.train_epochs,
+                       lr=2e-3, seed=2)
+    log("model loss", np.round(loss, 3))
+    b = api.Batch([g] * len(trees), trees, model=model)
+    tl, out = timed_steps(b.count, args.steps, args.warmup)
+    assert all(np.array_equal(a, r) for a, r in zip(out, ref))
+    tp, out = timed_steps(lambda: [api.count(g, tr) for tr in trees], args.steps, args.warmup)
+    assert all(np.array_equal(a, r) for a, r in zip(out, ref))
+    res = {
+        "metric": "root edges searched/s, learned + batched delta sweep (config 5), exact counts",
+        "value": len(trees) * E / tl, "unit": "root edges/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * tl,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32/u32, u64 counts; MLP bf16/fp32", "data": "synthetic",
+        "config": {"workload": "powerlaw V=%d E=%d gamma=2.0 span=1e8 s, 48 motifs of 3-5 "
+                               "edges, delta in %s" % (n, E, wl.deltas)},
+        "plain_ms": 1e3 * tp, "speedup_vs_plain": tp / tl, "train_loss": [float(x) for x in loss],
+        "batch": b.info(), "counts_total": [int(r.sum()) for r in ref],
+    }
+    if args.per_motif_steps:
+        tpm, out = timed_steps(lambda: [api.count(g, tr, mode="per_motif") for tr in trees], 1, 0)
+        assert all(np.array_equal(a, r) for a, r in zip(out, ref))
+        res["per_motif_ms"] = 1e3 * tpm
+        res["speedup_vs_per_motif"] = tpm / tl
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +268,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--queues", type=int, default=0, help="root queues (0 = one per XCD)")
     ap.add_argument("--chunk", type=int, default=0, help="roots per queue grab (0 = default)")
+    ap.add_argument("--config", type=int, default=2, choices=(2, 3, 4, 5),
+                    help="2: the headline single-graph benchmark (default); 3: batched; "
+                         "4: learned schedule; 5: learned + batched delta sweep")
+    ap.add_argument("--train-samples", type=int, default=200000)
+    ap.add_argument("--train-epochs", type=int, default=6)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -84,6 +288,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
+    if args.config == 3:
+        print(json.dumps(bench_batched(args)), flush=True)
+        return
+    if args.config == 4:
+        print(json.dumps(bench_learned(args)), flush=True)
+        return
+    if args.config == 5:
+        print(json.dumps(bench_sweep(args)), flush=True)
+        return
     if args.calibrate_copy:
         a = torch.ones(1 << 28, dtype=torch.int32, device="cuda")   # 1 GiB
         b = torch.empty_like(a)

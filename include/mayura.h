@@ -135,7 +135,10 @@ typedef struct {
     uint64_t *stats;          /* optional out, MG_NSTATS entries: search statistics
                                  (runs an instrumented kernel; not for timing) */
     int32_t sched;            /* MG_SCHED_PLAIN (default) or MG_SCHED_LEARNED */
-    int32_t reserved1;
+    int32_t leaf_scan;        /* windows up to this long whose children all end a
+                                 motif are counted by one lane: 0 = default (64),
+                                 < 0 = never (every window goes through the
+                                 wave-wide candidate expansion) */
     const struct mg_model *model;   /* cost model for MG_SCHED_LEARNED */
     uint64_t *root_cost;      /* optional out, n_edges entries indexed by root edge:
                                  1 + the candidate edges examined (window entries)
@@ -224,6 +227,10 @@ typedef struct {
     int32_t use_graph;        /* 1 = capture the step and replay it (default), 0 = plain launches */
     int32_t reserved;
     void *stream;             /* hipStream_t the steps run on (NULL = null stream) */
+    const struct mg_model *model;  /* optional: items are every job's 64-root segments
+                                      ordered by predicted cost across the batch,
+                                      costly ones split into single roots
+                                      (item_roots is then ignored) */
 } mg_batch_opts;
 void mg_batch_opts_init(mg_batch_opts *opts);
 int mg_batch_create(const mg_graph *const *graphs, const mg_tree *const *trees, int32_t n,
@@ -244,6 +251,7 @@ typedef struct {
     int32_t graph_captured;   /* 1 once a HIP graph replays the step */
     int32_t depth;            /* deepest tree */
     float tuned_ms;           /* best step time seen by the autotuner (0 if none) */
+    int32_t learned;          /* 1 when items come from the cost model */
 } mg_batch_info_t;
 int mg_batch_info(const mg_batch *b, mg_batch_info_t *out);
 void mg_batch_destroy(mg_batch *b);

@@ -53,7 +53,7 @@ class CountOpts(ctypes.Structure):
                 ("n_roots", ctypes.c_int64),
                 ("elapsed_ms", ctypes.POINTER(ctypes.c_float)),
                 ("stats", ctypes.c_void_p), ("sched", ctypes.c_int32),
-                ("reserved1", ctypes.c_int32), ("model", ctypes.c_void_p),
+                ("leaf_scan", ctypes.c_int32), ("model", ctypes.c_void_p),
                 ("root_cost", ctypes.c_void_p)]
 
 
@@ -63,7 +63,7 @@ STAT_NAMES = ("win_list", "win_all", "ent_list", "ent_all", "push", "credit", "r
 class BatchOpts(ctypes.Structure):
     _fields_ = [("blocks", ctypes.c_int32), ("item_roots", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("model", ctypes.c_void_p)]
 
 
 class BatchInfo(ctypes.Structure):
@@ -71,7 +71,7 @@ class BatchInfo(ctypes.Structure):
                 ("total_roots", ctypes.c_int64), ("n_items", ctypes.c_int64),
                 ("item_roots", ctypes.c_int32), ("blocks", ctypes.c_int32),
                 ("graph_captured", ctypes.c_int32), ("depth", ctypes.c_int32),
-                ("tuned_ms", ctypes.c_float)]
+                ("tuned_ms", ctypes.c_float), ("learned", ctypes.c_int32)]
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
@@ -262,7 +262,8 @@ class Tree:
 
 
 def count(graph: Graph, tree: Tree, mode="comine", roots=None, blocks=0, chunk=0,
-          queues=0, stream=None, timed=False, stats=False, root_cost=False, model=None):
+          queues=0, stream=None, timed=False, stats=False, root_cost=False, model=None,
+          leaf_scan=0):
     """Exact count per motif (``mg_count``), in the tree's motif order.
 
     ``mode``: "comine" (one search over the MG-Tree) or "per_motif" (one search
@@ -279,6 +280,7 @@ def count(graph: Graph, tree: Tree, mode="comine", roots=None, blocks=0, chunk=0
     o.blocks = int(blocks)
     o.chunk = int(chunk)
     o.queues = int(queues)
+    o.leaf_scan = int(leaf_scan)
     if model is not None:
         o.sched = 1
         o.model = model.handle.value
@@ -379,7 +381,8 @@ class Batch:
     """Many (graph, tree) jobs counted by one persistent launch, replayed as a
     captured HIP graph (``mg_batch_*``).  Keeps its graphs and trees alive."""
 
-    def __init__(self, graphs, trees, item_roots=0, blocks=0, use_graph=True, stream=None):
+    def __init__(self, graphs, trees, item_roots=0, blocks=0, use_graph=True, stream=None,
+                 model=None):
         L = lib()
         assert len(graphs) == len(trees) and len(graphs) > 0
         self._graphs, self._trees = list(graphs), list(trees)
@@ -389,6 +392,9 @@ class Batch:
         o.blocks = int(blocks)
         o.use_graph = 1 if use_graph else 0
         o.stream = _default_stream(stream)
+        if model is not None:
+            o.model = model.handle.value
+            self._model = model
         gh = (ctypes.c_void_p * len(graphs))(*[g.handle.value for g in graphs])
         th = (ctypes.c_void_p * len(trees))(*[t.handle.value for t in trees])
         h = ctypes.c_void_p()

@@ -14,6 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libmayura.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ROCM_INC = os.path.join(os.path.dirname(os.path.dirname(HIPCC)), "include")
 ARCH = "gfx950"
 
 # packed FP32 VALU ops stay off in every HIP compile
@@ -40,9 +41,10 @@ def build(verbose: bool = False) -> str:
         if verbose and out:
             print(out)
         objs.append(obj)
-    for name in ("host.cpp",):
+    for name in ("host.cpp",):   # host-only C++ (HIP runtime API, no device code)
         obj = os.path.join(BUILD_DIR, name + ".o")
-        out = _run([HIPCC, *COMMON, "-c", os.path.join(CSRC, name), "-o", obj])
+        out = _run([HIPCC, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I" + ROCM_INC, *COMMON, "-c",
+                    os.path.join(CSRC, name), "-o", obj])
         if verbose and out:
             print(out)
         objs.append(obj)

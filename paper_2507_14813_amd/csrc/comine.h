@@ -12,6 +12,7 @@ constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;
 constexpr int kQueues = 8;      // root queues, one per XCD
 constexpr int kQueueStride = 16;  // u64 words between queue heads (own cache line)
+constexpr uint32_t kLeafScanDefault = 64;
 
 // group direction: which adjacency list holds the candidates
 enum : int { kDirOut = 0, kDirIn = 1, kDirAll = 2 };
@@ -19,7 +20,9 @@ enum : int { kDirOut = 0, kDirIn = 1, kDirAll = 2 };
 // Search tables, as uploaded to the device.
 //   inode[i]  internal (non-leaf) trie node i: first group | group count << 20
 //   grp[2g], grp[2g+1]: eight words of group g:
-//     w0 = dir | anchor << 4 | nv << 8   (nv: vertices bound at the owning node)
+//     w0 = dir | anchor << 4 | nv << 8 | leaf_only << 12
+//          (nv: vertices bound at the owning node; leaf_only: a per-vertex
+//          list whose children all end a motif)
 //     w1..w6 = child reached when the scanned endpoint is bound motif vertex 0..5
 //     w7 = child reached when the scanned endpoint(s) are new vertices
 //   A child word is 0 when there is no such child, else
@@ -67,6 +70,8 @@ struct KParams {
                                     // examined below that root (zeroed before launch)
     const uint2 *items;           // NULL, or work items {first, end} of root positions
     const uint32_t *n_items;      // device count of items (with items)
+    uint32_t leaf_scan;           // windows up to this long whose children are all
+                                  // leaves are counted by one lane (0: never)
 };
 
 // search statistics (schedule independent), filled when KParams::stats is set
@@ -105,6 +110,7 @@ struct BatchParams {
     uint32_t n_q_max;             // largest tree's counter count
     unsigned long long *cursor;   // item queue head, zeroed before launch
     unsigned long long *counts;   // every job's counters, zeroed before launch
+    uint32_t leaf_scan;           // as KParams::leaf_scan
 };
 
 // `depth` = the deepest tree of the batch.

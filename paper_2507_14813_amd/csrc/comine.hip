@@ -55,6 +55,44 @@ __device__ __forceinline__ uint32_t child_word(const uint4 &a, const uint4 &b, i
     return r;
 }
 
+__device__ __forceinline__ uint32_t credit_child(uint32_t word, uint32_t c,
+                                                unsigned long long *cnt) {
+    if (!c || !word) return 0;
+    const uint32_t q1 = (word >> 16) & 0x7fffu;
+    if (q1) atomicAdd(&cnt[q1 - 1], (unsigned long long)c);
+    return c;
+}
+
+// Counts a leaf-only window [l0, l0 + len) of one adjacency list for the
+// partial match with bound vertices ph[0..nvp): each entry reaches the child
+// of the bound vertex it hits, or the new-vertex child.  Returns the credits.
+template <typename TT, int SA>
+__device__ __forceinline__ uint32_t leaf_scan_window(const Entry<TT> *__restrict__ adj,
+                                                     uint32_t l0, uint32_t len,
+                                                     const int32_t (&ph)[SA], uint32_t nvp,
+                                                     const uint4 ga, const uint4 gb,
+                                                     unsigned long long *cnt) {
+    uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0, cn = 0;
+    auto tally = [&](int32_t v) {
+        int y = -1;
+#pragma unroll
+        for (int s = 0; s < SA; ++s) y = ((uint32_t)s < nvp && ph[s] == v) ? s : y;
+        c0 += y == 0; c1 += y == 1; c2 += y == 2; c3 += y == 3; c4 += y == 4; c5 += y == 5;
+        cn += y < 0;
+    };
+    const Entry<TT> *e = adj + l0;
+    uint32_t i = 0;
+    for (; i + 4 <= len; i += 4) {
+        const int32_t v0 = e[i].v, v1 = e[i + 1].v, v2 = e[i + 2].v, v3 = e[i + 3].v;
+        tally(v0); tally(v1); tally(v2); tally(v3);
+    }
+    for (; i < len; ++i) tally(e[i].v);
+    return credit_child(ga.y, c0, cnt) + credit_child(ga.z, c1, cnt) +
+           credit_child(ga.w, c2, cnt) + credit_child(gb.x, c3, cnt) +
+           credit_child(gb.y, c4, cnt) + credit_child(gb.z, c5, cnt) +
+           credit_child(gb.w, cn, cnt);
+}
+
 // Partial matches with L motif edges matched.  Level 1 is the root batch:
 // every entry is at the trie root and its last edge is its first, so it keeps
 // only the two bound vertices and the root time.
@@ -150,7 +188,7 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
             } else {
                 // one (partial match, group) pair per lane -> its window
                 const uint32_t pi = pc + lane;
-                uint32_t len = 0, x = 0, g = 0, l0 = 0;
+                uint32_t len = 0, x = 0, g = 0, l0 = 0, hdr = 0;
                 bool all = false;
                 if (pi < P) {
                     uint32_t lo = 0;
@@ -171,7 +209,7 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                         tp = A.tprev[lo];
                     }
                     x = lo;
-                    const uint32_t hdr = grp[2 * g].x;
+                    hdr = grp[2 * g].x;
                     const int dir = hdr & 15, anc = (hdr >> 4) & 15;
                     const TT thi = sat_add(A.tfirst[lo], p.delta_sat);
                     uint32_t b, e, sh;
@@ -203,8 +241,21 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                     if (take && len > 0)
                         atomicAdd(&p.root_cost[A.root[x]], (unsigned long long)len);
                 }
-                // compact the non-empty windows into lanes 0..nw-1
-                const bool keep = take && len > 0;
+                // a short window whose children are all leaves is counted by
+                // its own lane: independent loads, counts kept per child
+                bool scanned = false;
+                if (take && len > 0 && len <= p.leaf_scan && ((hdr >> 12) & 1)) {
+                    scanned = true;
+                    int32_t ph[SA];
+#pragma unroll
+                    for (int s = 0; s < SA; ++s) ph[s] = A.phi[s][x];
+                    const uint32_t c = leaf_scan_window<TT, SA>(
+                        (hdr & 15) == kDirOut ? p.g.out_adj : p.g.in_adj, l0, len, ph,
+                        (hdr >> 8) & 15, grp[2 * g], grp[2 * g + 1], cnt);
+                    if constexpr (STATS) st.v[kStatCredit] += c;
+                }
+                // compact the other non-empty windows into lanes 0..nw-1
+                const bool keep = take && len > 0 && !scanned;
                 const uint64_t km = __ballot(keep);
                 nw = uniform((uint32_t)__popcll(km));
                 if (keep) W.src[mbcnt(km)] = (uint8_t)lane;
@@ -452,6 +503,7 @@ batch_kernel(const BatchParams<TT> bp) {
         p.tree = job.tree;
         p.delta_sat = job.delta_sat;
         p.roots = nullptr;
+        p.leaf_scan = bp.leaf_scan;
         const uint32_t nq = (uint32_t)p.tree.n_q;
         for (uint32_t i = (uint32_t)lane; i < nq; i += kWave) cnt[i] = 0;
         wave_sync();

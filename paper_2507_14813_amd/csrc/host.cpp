@@ -279,7 +279,10 @@ int build_tree(mg_tree *tr) {
         if (g0 + (int)groups.size() > (1 << 20))
             return fail(MG_EUNSUPPORTED, "too many child groups");
         for (auto &kv : groups) {
-            int32_t rec[8] = {kv.first.first | (kv.first.second << 4) | (nd.nv << 8),
+            bool leaf_only = kv.first.first != mg::kDirAll;
+            for (int c : kv.second) leaf_only = leaf_only && tr->nodes[c].kids.empty();
+            int32_t rec[8] = {kv.first.first | (kv.first.second << 4) | (nd.nv << 8) |
+                                  ((leaf_only ? 1 : 0) << 12),
                               0, 0, 0, 0, 0, 0, 0};
             for (int c : kv.second) {
                 const TrieNode &ch = tr->nodes[c];
@@ -398,6 +401,8 @@ int launch_tree(const mg_graph *g, mg_tree *tr, const uint32_t *d_roots, uint32_
     p.n_roots = n_roots;
     p.chunk = (uint32_t)(o.chunk > 0 ? o.chunk : 64);
     p.n_queues = (uint32_t)(o.queues > 0 ? o.queues : mg::kQueues);
+    p.leaf_scan = o.leaf_scan < 0 ? 0u : (o.leaf_scan == 0 ? mg::kLeafScanDefault
+                                                           : (uint32_t)o.leaf_scan);
     p.queues = d_queues;
     p.counts = d_counts;
     p.stats = d_stats;
@@ -545,6 +550,7 @@ struct mg_batch {
     mg_batch_opts opts{};
     int32_t item_roots = 0;
     float tuned_ms = 0.f;
+    bool learned = false;
     std::vector<mg::BatchItem> items;
     DevBuf d_jobs, d_items, d_work;   // d_work: cursor (16 B) + counters
     uint64_t *h_counts = nullptr;     // pinned
@@ -620,6 +626,75 @@ int make_items(mg_batch *b, int32_t item_roots, hipStream_t st) {
     return MG_OK;
 }
 
+// Items from predicted costs: every job's 64-root segments, heaviest first
+// across the whole batch; a segment worth more than a quarter of one wave's
+// fair share of the predicted total is split into single roots.
+template <typename TT>
+int predict_job_segments(const mg_graph *g, mg_tree *tr, const mg_model *m, float *d_seg,
+                         float *d_total, hipStream_t st) {
+    hipError_t e = mg::launch_fill_f32_zero(d_total, 1, st);
+    if (e == hipSuccess)
+        e = mg::launch_predict_roots<TT>(dev_graph<TT>(g), dev_tree(tr), delta_sat<TT>(tr->delta),
+                                         (const float *)m->params.ptr, d_seg, d_total, st);
+    if (e != hipSuccess) return fail(MG_EDEVICE, "cost prediction failed: %s", hipGetErrorString(e));
+    return MG_OK;
+}
+
+int learned_items(mg_batch *b, const mg_model *m, hipStream_t st) {
+    struct Seg { float cost; uint32_t job, first, end; };
+    std::vector<Seg> segs;
+    double total = 0.0;
+    for (size_t j = 0; j < b->graphs.size(); ++j) {
+        const mg_graph *g = b->graphs[j];
+        const uint32_t E = (uint32_t)g->E, n_seg = (E + mg::kSeg - 1) / mg::kSeg;
+        if (!n_seg) continue;
+        DevBuf d;
+        int rc = dev_alloc(d, 4 * (size_t)n_seg + 16, (void *)st);
+        if (rc) return rc;
+        struct G { DevBuf *b; ~G() { dev_free(*b); } } guard{&d};
+        float *d_seg = (float *)d.ptr, *d_total = d_seg + n_seg;
+        rc = b->time_bytes == 4 ? predict_job_segments<uint32_t>(g, b->trees[j], m, d_seg, d_total, st)
+                                : predict_job_segments<uint64_t>(g, b->trees[j], m, d_seg, d_total, st);
+        if (rc) return rc;
+        std::vector<float> h(n_seg);
+        HIP_TRY(hipMemcpyAsync(h.data(), d_seg, 4 * (size_t)n_seg, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (uint32_t sg = 0; sg < n_seg; ++sg) {
+            const uint32_t r0 = sg * mg::kSeg;
+            segs.push_back({h[sg], (uint32_t)j, r0, std::min<uint32_t>(E, r0 + mg::kSeg)});
+            total += h[sg];
+        }
+    }
+    int dev = 0, ncu = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    const double split = total / (4.0 * 32.0 * std::max(ncu, 1));   // ~32 resident waves per CU
+    std::vector<std::pair<float, mg::BatchItem>> it;
+    it.reserve(segs.size());
+    for (const Seg &sg : segs) {
+        if (sg.cost > split && sg.end - sg.first > 1) {
+            const float c = sg.cost / (float)(sg.end - sg.first);
+            for (uint32_t r = sg.first; r < sg.end; ++r) it.push_back({c, {sg.job, r, r + 1, 0u}});
+        } else {
+            it.push_back({sg.cost, {sg.job, sg.first, sg.end, 0u}});
+        }
+    }
+    std::stable_sort(it.begin(), it.end(),
+                     [](const auto &x, const auto &y) { return x.first > y.first; });
+    b->items.clear();
+    for (auto &x : it) b->items.push_back(x.second);
+    dev_free(b->d_items);
+    int rc = dev_alloc(b->d_items, sizeof(mg::BatchItem) * std::max<size_t>(1, b->items.size()),
+                       (void *)st);
+    if (rc) return rc;
+    if (!b->items.empty())
+        HIP_TRY(hipMemcpyAsync(b->d_items.ptr, b->items.data(),
+                               sizeof(mg::BatchItem) * b->items.size(), hipMemcpyHostToDevice, st));
+    b->item_roots = mg::kSeg;
+    b->learned = true;
+    return MG_OK;
+}
+
 // Enqueue one step on st: zero, search, copy the counters to pinned memory.
 template <typename TT>
 int enqueue_step(mg_batch *b, hipStream_t st) {
@@ -630,6 +705,7 @@ int enqueue_step(mg_batch *b, hipStream_t st) {
     bp.n_q_max = b->n_q_max;
     bp.cursor = (unsigned long long *)b->d_work.ptr;
     bp.counts = (unsigned long long *)((char *)b->d_work.ptr + 16);
+    bp.leaf_scan = mg::kLeafScanDefault;
     hipError_t e = mg::launch_fill_u64(bp.cursor, 2 + b->total_q, 0ull, st);
     if (e != hipSuccess) return fail(MG_EDEVICE, "fill launch failed: %s", hipGetErrorString(e));
     if (bp.n_items) {
@@ -869,6 +945,7 @@ int mg_batch_create(const mg_graph *const *graphs, const mg_tree *const *trees, 
             return fail(MG_EINVAL, "item_roots must be a multiple of 64 in [0, 2^24]");
         int dev = 0;
         HIP_TRY(hipGetDevice(&dev));
+        if (o.model && o.model->device != dev) return fail(MG_EINVAL, "model on another device");
         std::unique_ptr<mg_batch> b(new (std::nothrow) mg_batch);
         if (!b) return fail(MG_ENOMEM, "out of host memory");
         b->opts = o;
@@ -899,26 +976,37 @@ int mg_batch_create(const mg_graph *const *graphs, const mg_tree *const *trees, 
         if (rc) return rc;
         HIP_TRY(hipHostMalloc((void **)&b->h_counts, 8 * (size_t)std::max<uint32_t>(1, b->total_q),
                               hipHostMallocDefault));
-        if (o.item_roots > 0) {
+        if (o.model) {
+            rc = learned_items(b.get(), o.model, st);
+            if (rc) return rc;
+        } else if (o.item_roots > 0) {
             rc = make_items(b.get(), o.item_roots, st);
             if (rc) return rc;
         } else {
-            // autotune the item size: time one step per candidate, keep the best
+            // autotune the item size: one timed step per candidate, from small
+            // to large, stopping at the first one that is clearly slower
             float best = -1.f;
             int32_t best_ir = 64;
-            for (int32_t ir : {64, 128, 256, 512, 2048}) {
+            bool warm = false;
+            for (int32_t ir : {64, 128, 256, 512, 1024}) {
                 rc = make_items(b.get(), ir, st);
                 if (rc) return rc;
+                if (!warm) {
+                    rc = run_step(b.get(), st, nullptr);
+                    if (rc) return rc;
+                    warm = true;
+                }
                 float ms = 0.f;
-                rc = run_step(b.get(), st, nullptr);   // warm
-                if (rc) return rc;
                 rc = run_step(b.get(), st, &ms);
                 if (rc) return rc;
                 if (best < 0.f || ms < best) { best = ms; best_ir = ir; }
+                else if (ms > 1.05f * best) break;
             }
             b->tuned_ms = best;
-            rc = make_items(b.get(), best_ir, st);
-            if (rc) return rc;
+            if (b->item_roots != best_ir) {
+                rc = make_items(b.get(), best_ir, st);
+                if (rc) return rc;
+            }
         }
         HIP_TRY(hipStreamSynchronize(st));
         *out = b.release();
@@ -967,6 +1055,7 @@ int mg_batch_info(const mg_batch *b, mg_batch_info_t *out) {
     out->graph_captured = b->exec ? 1 : 0;
     out->depth = b->depth;
     out->tuned_ms = b->tuned_ms;
+    out->learned = b->learned ? 1 : 0;
     return MG_OK;
 }
 

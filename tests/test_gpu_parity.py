@@ -96,9 +96,11 @@ def test_medium_graph_all_modes(delta):
     say("medium", delta)
     assert np.array_equal(api.count(g, tr), want)
     assert np.array_equal(api.count(g, tr, mode="per_motif"), want)
-    for blocks, chunk, queues in ((1, 64, 0), (3, 128, 1), (0, 1024, 3), (0, 64, 8), (9, 192, 0)):
-        say("schedule", blocks, chunk, queues)
-        assert np.array_equal(api.count(g, tr, blocks=blocks, chunk=chunk, queues=queues), want)
+    for blocks, chunk, queues, ls in ((1, 64, 0, 0), (3, 128, 1, -1), (0, 1024, 3, 7),
+                                      (0, 64, 8, 1000), (9, 192, 0, 1)):
+        say("schedule", blocks, chunk, queues, ls)
+        assert np.array_equal(api.count(g, tr, blocks=blocks, chunk=chunk, queues=queues,
+                                        leaf_scan=ls), want)
     roots = np.arange(5, len(s), 7)
     say("roots subset")
     assert np.array_equal(api.count(g, tr, roots=roots), oracle_counts(og, ms, delta, roots))
@@ -309,6 +311,34 @@ def test_config2_full_size_sampled_roots():
     # single-edge count of the whole graph is the number of non-self-loop edges
     one = api.count(g, api.Tree([[(0, 1)]], delta))
     assert int(one[0]) == int((s != d).sum())
+
+
+@pytest.mark.parametrize("k,scale,n_sample", [(4, 1.0, 2048), (5, 0.1, 4096), (3, 1.0, 0)])
+def test_large_configs_sampled_roots(k, scale, n_sample):
+    """Configuration-scale graphs (config 4 at full size, 50M edges; config 5
+    at a tenth; config 3's largest graphs), counts on sampled roots against
+    the oracle, plus co-mine == per-motif on the sample."""
+    wl = W.make_config(k, scale=scale)
+    rng = np.random.default_rng(k)
+    jobs = list(range(len(wl.graphs)))
+    if k == 3:   # the three largest graphs of the batch
+        jobs = sorted(jobs, key=lambda j: -len(wl.graphs[j][0]))[:3]
+    for j in jobs:
+        s, d, t, n = wl.graphs[j]
+        ms = wl.motif_sets[j]
+        E = len(s)
+        ns = n_sample or 4096
+        roots = np.sort(rng.choice(E, min(E, ns), replace=False))
+        og = OracleGraph(s, d, t, n)
+        g = api.Graph(s, d, t, n)
+        for delta in wl.deltas if k == 5 else [wl.deltas[j]]:
+            tr = api.Tree(ms, delta)
+            say("config", k, "job", j, "E", E, "delta", delta)
+            want = oracle_counts(og, ms, delta, roots)
+            assert np.array_equal(api.count(g, tr, roots=roots), want), (k, j, delta)
+            assert np.array_equal(api.count(g, tr, roots=roots, mode="per_motif"), want)
+        og.close()
+        g.close()
 
 
 def test_edge_cases(oracle_mod):

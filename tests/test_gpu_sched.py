@@ -193,3 +193,25 @@ def test_learned_schedule_counts_are_exact():
     tr = api.Tree(wl.motif_sets[0], wl.deltas[0])
     say("learned schedule config-2 mini")
     assert np.array_equal(api.count(g, tr, model=m), api.count(g, tr))
+
+
+def test_learned_batch_counts_are_exact():
+    rng = np.random.default_rng(6)
+    graphs, trees, want = [], [], []
+    for j in range(5):
+        n = int(rng.integers(8, 50))
+        s, d, t = tiny_graph(rng, n, int(rng.integers(100, 4000)), int(rng.integers(100, 3000)),
+                             self_loops=True)
+        ms = W.random_extension_motifs(int(rng.integers(3, 10)), (2, 3, 4), 5, 70 + j)
+        delta = int(rng.integers(5, 150))
+        og = OracleGraph(s, d, t, n)
+        graphs.append(api.Graph(s, d, t, n))
+        trees.append(api.Tree(ms, delta))
+        want.append(np.array([og.count(x, delta) for x in ms], dtype=np.uint64))
+    m = api.Model(seed=4)
+    say("learned batch")
+    b = api.Batch(graphs, trees, model=m)
+    assert b.info()["learned"] == 1
+    for _ in range(3):
+        for a, w in zip(b.count(), want):
+            assert np.array_equal(a, w)
