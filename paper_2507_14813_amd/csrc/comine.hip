@@ -254,18 +254,21 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                         (hdr >> 8) & 15, grp[2 * g], grp[2 * g + 1], cnt);
                     if constexpr (STATS) st.v[kStatCredit] += c;
                 }
-                // compact the other non-empty windows into lanes 0..nw-1
+                // compact the other non-empty windows into lanes 0..nw-1; their
+                // candidate ranges are numbered without the lane-counted ones
+                // (the chunk total stays below the limit checked above)
                 const bool keep = take && len > 0 && !scanned;
+                const uint32_t lk = keep ? len : 0u;
+                const uint32_t incl = incl_scan32(lk, lane);
                 const uint64_t km = __ballot(keep);
                 nw = uniform((uint32_t)__popcll(km));
                 if (keep) W.src[mbcnt(km)] = (uint8_t)lane;
                 wave_sync();
                 const int from = (uint32_t)lane < nw ? (int)W.src[lane] : lane;
                 wave_sync();
-                const uint32_t incl = (uint32_t)incl64;
                 wrec.x = __shfl(x | (g << 8), from);
                 wrec.y = __shfl(l0, from);
-                wrec.z = __shfl(incl - len, from);
+                wrec.z = __shfl(incl - lk, from);
                 wrec.w = __shfl(incl, from);
                 if ((uint32_t)lane >= nw) wrec = make_uint4(0, 0, 0, 0);
                 T = nw ? uniform(__shfl(wrec.w, (int)nw - 1)) : 0u;
