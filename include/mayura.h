@@ -136,9 +136,9 @@ typedef struct {
                                  (runs an instrumented kernel; not for timing) */
     int32_t sched;            /* MG_SCHED_PLAIN (default) or MG_SCHED_LEARNED */
     int32_t leaf_scan;        /* windows up to this long whose children all end a
-                                 motif are counted by one lane: 0 = default (64),
-                                 < 0 = never (every window goes through the
-                                 wave-wide candidate expansion) */
+                                 motif are counted by one lane: 0 = default (no
+                                 limit), < 0 = never (every window goes through
+                                 the wave-wide candidate expansion) */
     const struct mg_model *model;   /* cost model for MG_SCHED_LEARNED */
     uint64_t *root_cost;      /* optional out, n_edges entries indexed by root edge:
                                  1 + the candidate edges examined (window entries)
@@ -159,9 +159,11 @@ typedef struct {
 
 /* schedules (what runs where; never what is counted) */
 #define MG_SCHED_PLAIN 0      /* roots in time order, 64-root chunks from XCD queues */
-#define MG_SCHED_LEARNED 1    /* an MLP predicts every root's cost; time-local
-                                 64-root segments run heaviest first, costly
-                                 segments split into single roots */
+#define MG_SCHED_LEARNED 1    /* an MLP predicts the cost of every 64-root
+                                 segment; segments above 8x the mean run first,
+                                 heaviest first (the costliest split into single
+                                 roots), then the rest in time order from one
+                                 queue (ignores chunk and queues) */
 
 /* Fill opts with the defaults (co-mining, all roots, null stream). */
 void mg_count_opts_init(mg_count_opts *opts);

@@ -125,13 +125,21 @@ struct LevelChain {
 template <typename TT, int D, bool R>
 struct LevelChain<TT, D, R, D> {};
 
-// per-wave LDS: level buffers plus two 64-byte scratch tables
+// per-wave LDS: level buffers plus two 64-byte scratch tables.  Its size is a
+// multiple of 16 bytes, so that per-wave blocks laid out back to back (with
+// 64-bit counters between them) keep those counters 8-byte aligned, as LDS
+// 64-bit atomics require.
 template <typename TT, int D, bool R>
-struct WaveLds {
+struct alignas(16) WaveLds {
     uint8_t src[kWave];           // window compaction: lane holding the k-th window
     uint8_t flag[kWave];          // window-end marks of one pass
     LevelChain<TT, D, R, 1> lv;
 };
+
+static_assert(sizeof(WaveLds<uint32_t, 1, false>) % 16 == 0, "per-wave LDS block size");
+static_assert(sizeof(WaveLds<uint32_t, 3, false>) % 16 == 0, "per-wave LDS block size");
+static_assert(sizeof(WaveLds<uint32_t, 5, false>) % 16 == 0, "per-wave LDS block size");
+static_assert(sizeof(WaveLds<uint64_t, 5, true>) % 16 == 0, "per-wave LDS block size");
 
 template <int L, typename TT, int D, bool R, int M>
 __device__ __forceinline__ LevelBuf<TT, L, R> &lvl(LevelChain<TT, D, R, M> &c) {
@@ -440,11 +448,11 @@ comine_kernel(const KParams<TT> p) {
     for (int i = 0; i < kStats; ++i) st.v[i] = 0;
 
     if (p.items) {
-        // scheduled work items, claimed in order from one queue
+        // scheduled work items first, claimed in order from their own queue
         const uint32_t n_items = uniform(*p.n_items);
         for (;;) {
             unsigned long long it = 0;
-            if (lane == 0) it = atomicAdd(&p.queues[0], 1ull);
+            if (lane == 0) it = atomicAdd(&p.queues[kQueues * kQueueStride], 1ull);
             it = __shfl(it, 0);
             if (it >= n_items) break;
             const uint2 item = p.items[uniform((uint32_t)it)];
@@ -453,8 +461,8 @@ comine_kernel(const KParams<TT> p) {
     }
     // workgroups are dispatched to the XCDs round-robin: start on this XCD's
     // share of the roots, then take what is left of the others
-    const uint32_t nq = p.items ? 0u : p.n_queues;
-    const uint32_t home = nq ? blockIdx.x % nq : 0u;
+    const uint32_t nq = p.n_queues;
+    const uint32_t home = blockIdx.x % nq;
     for (uint32_t qi = 0; qi < nq; ++qi) {
         const uint32_t q = (home + qi) % nq;
         const uint32_t qbeg = (uint32_t)(((uint64_t)p.n_roots * q) / nq);
@@ -465,6 +473,7 @@ comine_kernel(const KParams<TT> p) {
             got = __shfl(got, 0);
             if (got >= (unsigned long long)(qend - qbeg)) break;
             const uint32_t base = uniform(qbeg + (uint32_t)got);
+            if (p.skip && p.skip[base / kWave]) continue;   // searched as an item
             process_roots<TT, D, MODE>(p, W, cnt, lane, base, min(base + p.chunk, qend), st);
         }
     }

@@ -21,7 +21,8 @@
 
 using mg::kVMax;
 using mg::kKMax;
-constexpr size_t kQueueBytes = sizeof(unsigned long long) * mg::kQueues * mg::kQueueStride;
+// kQueues root-queue heads plus one work-item queue head
+constexpr size_t kQueueBytes = sizeof(unsigned long long) * (mg::kQueues + 1) * mg::kQueueStride;
 
 namespace {
 
@@ -507,25 +508,35 @@ int learned_search(const mg_graph *g, mg_tree *tr, const mg_model *model,
     const size_t off_work = off_total + 16;
     const size_t off_nitems = off_work + 4 * (size_t)mg::kBinWords;
     const size_t off_items = (off_nitems + 16 + 15) & ~(size_t)15;
-    int rc = dev_alloc(d, off_items + 8 * (size_t)std::max<uint32_t>(E, 1), (void *)st);
+    const size_t off_feat = (off_items + 8 * (size_t)std::max<uint32_t>(E, 1) + 15) & ~(size_t)15;
+    const size_t off_skip = off_feat + 32 * (size_t)std::max<uint32_t>(E, 1);
+    int rc = dev_alloc(d, off_skip + n_seg + 16, (void *)st);
     if (rc) return rc;
     struct G { DevBuf *b; ~G() { dev_free(*b); } } guard{&d};
     char *p0 = (char *)d.ptr;
     float *seg_cost = (float *)p0, *total = (float *)(p0 + off_total);
     uint32_t *work = (uint32_t *)(p0 + off_work), *n_items = (uint32_t *)(p0 + off_nitems);
     uint2 *items = (uint2 *)(p0 + off_items);
+    uint4 *feat = (uint4 *)(p0 + off_feat);
+    uint8_t *skip = (uint8_t *)(p0 + off_skip);
     hipError_t e = mg::launch_fill_f32_zero(total, 1, st);
     if (e == hipSuccess)
         e = mg::launch_predict_roots<TT>(base.g, base.tree, base.delta_sat,
-                                         (const float *)model->params.ptr, seg_cost, total, st);
-    // a segment worth more than ~1/(4 * resident waves) of the predicted total is split
+                                         (const float *)model->params.ptr, seg_cost, total, feat,
+                                         st);
+    // segments predicted at more than 8x the mean go first (one root per item
+    // above ~1/(4 * resident waves) of the total); the rest keep time order
     if (e == hipSuccess)
-        e = mg::launch_bin(seg_cost, n_seg, E, total, 1.0f / 32768.0f, work, items, n_items, st);
+        e = mg::launch_bin(seg_cost, n_seg, E, total, 8.0f, 1.0f / 32768.0f, work, items, n_items,
+                           skip, st);
     if (e != hipSuccess) return fail(MG_EDEVICE, "learned schedule failed: %s", hipGetErrorString(e));
     mg::KParams<TT> p = base;
     p.items = items;
     p.n_items = n_items;
+    p.skip = skip;
     p.roots = nullptr;
+    p.n_queues = 1;          // 64-root chunks stay aligned with the segments
+    p.chunk = mg::kSeg;
     e = mg::launch_comine<TT>(p, blocks, st);
     if (e != hipSuccess) return fail(MG_EDEVICE, "co-mining launch failed: %s", hipGetErrorString(e));
     // the buffer is released after the caller synchronises the stream
@@ -631,11 +642,11 @@ int make_items(mg_batch *b, int32_t item_roots, hipStream_t st) {
 // fair share of the predicted total is split into single roots.
 template <typename TT>
 int predict_job_segments(const mg_graph *g, mg_tree *tr, const mg_model *m, float *d_seg,
-                         float *d_total, hipStream_t st) {
+                         float *d_total, uint4 *d_feat, hipStream_t st) {
     hipError_t e = mg::launch_fill_f32_zero(d_total, 1, st);
     if (e == hipSuccess)
         e = mg::launch_predict_roots<TT>(dev_graph<TT>(g), dev_tree(tr), delta_sat<TT>(tr->delta),
-                                         (const float *)m->params.ptr, d_seg, d_total, st);
+                                         (const float *)m->params.ptr, d_seg, d_total, d_feat, st);
     if (e != hipSuccess) return fail(MG_EDEVICE, "cost prediction failed: %s", hipGetErrorString(e));
     return MG_OK;
 }
@@ -649,12 +660,15 @@ int learned_items(mg_batch *b, const mg_model *m, hipStream_t st) {
         const uint32_t E = (uint32_t)g->E, n_seg = (E + mg::kSeg - 1) / mg::kSeg;
         if (!n_seg) continue;
         DevBuf d;
-        int rc = dev_alloc(d, 4 * (size_t)n_seg + 16, (void *)st);
+        const size_t off_feat = (4 * (size_t)n_seg + 16 + 15) & ~(size_t)15;
+        int rc = dev_alloc(d, off_feat + 32 * (size_t)E, (void *)st);
         if (rc) return rc;
         struct G { DevBuf *b; ~G() { dev_free(*b); } } guard{&d};
         float *d_seg = (float *)d.ptr, *d_total = d_seg + n_seg;
-        rc = b->time_bytes == 4 ? predict_job_segments<uint32_t>(g, b->trees[j], m, d_seg, d_total, st)
-                                : predict_job_segments<uint64_t>(g, b->trees[j], m, d_seg, d_total, st);
+        uint4 *d_feat = (uint4 *)((char *)d.ptr + off_feat);
+        rc = b->time_bytes == 4
+                 ? predict_job_segments<uint32_t>(g, b->trees[j], m, d_seg, d_total, d_feat, st)
+                 : predict_job_segments<uint64_t>(g, b->trees[j], m, d_seg, d_total, d_feat, st);
         if (rc) return rc;
         std::vector<float> h(n_seg);
         HIP_TRY(hipMemcpyAsync(h.data(), d_seg, 4 * (size_t)n_seg, hipMemcpyDeviceToHost, st));

@@ -35,23 +35,26 @@ hipError_t launch_features(const DevGraph<TT> &g, const DevTree &t, TT delta_sat
 hipError_t launch_predict_feats(const float *params, const float *feats, uint32_t n, float *out,
                                 hipStream_t st);
 
-// Fused: features + MLP for every root edge; per 64-root segment writes the
-// sum of exp(prediction) (predicted cost) to seg_cost[n_edges / 64 rounded up]
-// and adds every segment to *total (zeroed by the caller).
+// Features (into feat_buf: 32 bytes per root edge) then the MLP for every
+// root edge; per 64-root segment writes the sum of exp(prediction) (predicted
+// cost) to seg_cost[n_edges / 64 rounded up] and adds every segment to *total
+// (zeroed by the caller).
 template <typename TT>
 hipError_t launch_predict_roots(const DevGraph<TT> &g, const DevTree &t, TT delta_sat,
                                 const float *params, float *seg_cost, float *total,
-                                hipStream_t st);
+                                uint4 *feat_buf, hipStream_t st);
 
-// Binning: from segment costs, write work items {begin, end} (root ranges),
-// heaviest cost bin first; a segment costlier than split_frac * (*total)
-// becomes one item per root.  work: scratch of kBinWords u32 (zeroed here);
-// items: capacity n_roots; n_items_out: device u32.
+// Binning: segments predicted to cost more than heavy_mult times the mean
+// segment become work items {begin, end} (root ranges), heaviest cost bin
+// first, and are flagged in skip[n_seg] (when skip is not NULL); a heavy
+// segment costlier than split_frac * (*total) becomes one item per root.
+// work: scratch of kBinWords u32 (zeroed here); items: capacity n_roots;
+// n_items_out: device u32.  heavy_mult = 0 makes every segment an item.
 constexpr int kBins = 48;
 constexpr int kBinWords = 3 * kBins + 4;
 hipError_t launch_bin(const float *seg_cost, uint32_t n_seg, uint32_t n_roots, const float *total,
-                      float split_frac, uint32_t *work, uint2 *items, uint32_t *n_items_out,
-                      hipStream_t st);
+                      float heavy_mult, float split_frac, uint32_t *work, uint2 *items,
+                      uint32_t *n_items_out, uint8_t *skip, hipStream_t st);
 
 // p[0..n) = 0 with a kernel
 hipError_t launch_fill_f32_zero(float *p, uint32_t n, hipStream_t st);

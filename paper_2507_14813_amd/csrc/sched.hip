@@ -227,11 +227,34 @@ predict_feats_kernel(const float *P, const float *feats, uint32_t n, float *out)
     }
 }
 
-// Fused features + MLP over every root; one 64-root segment per wave step.
+// Features of every root as 16 BF16 values (two 16-byte words per root).
 template <typename TT>
+__global__ void __launch_bounds__(256)
+features_pack_kernel(const DevGraph<TT> g, const DevTree t, TT dsat, uint4 *out) {
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < g.n_edges;
+         r += gridDim.x * blockDim.x) {
+        float f[kFeat];
+        root_features(g, t, dsat, r, f);
+        uint4 a, b;
+        a.x = f2bf(f[0]) | ((uint32_t)f2bf(f[1]) << 16);
+        a.y = f2bf(f[2]) | ((uint32_t)f2bf(f[3]) << 16);
+        a.z = f2bf(f[4]) | ((uint32_t)f2bf(f[5]) << 16);
+        a.w = f2bf(f[6]) | ((uint32_t)f2bf(f[7]) << 16);
+        b.x = f2bf(f[8]) | ((uint32_t)f2bf(f[9]) << 16);
+        b.y = f2bf(f[10]) | ((uint32_t)f2bf(f[11]) << 16);
+        b.z = f2bf(f[12]) | ((uint32_t)f2bf(f[13]) << 16);
+        b.w = f2bf(f[14]) | ((uint32_t)f2bf(f[15]) << 16);
+        out[2 * (size_t)r] = a;
+        out[2 * (size_t)r + 1] = b;
+    }
+}
+
+// MLP over packed features, one 64-root segment per wave step: writes the
+// segment's predicted cost (sum of exp(prediction) over searched roots) and
+// adds it to *total.
 __global__ void __launch_bounds__(kWave * kPredWaves)
-predict_roots_kernel(const DevGraph<TT> g, const DevTree t, TT dsat, const float *P,
-                     float *seg_cost, uint32_t n_seg, float *total) {
+mlp_segments_kernel(const float *P, const uint4 *feats, uint32_t n_roots, float *seg_cost,
+                    uint32_t n_seg, float *total) {
     __shared__ __align__(16) uint16_t Xs[kPredWaves][64 * 32];
     __shared__ __align__(16) uint16_t Hs[kPredWaves][16 * kHid];
     __shared__ float Ps[kPredWaves][64];
@@ -241,16 +264,26 @@ predict_roots_kernel(const DevGraph<TT> g, const DevTree t, TT dsat, const float
     float tsum = 0.f;
     for (uint32_t seg = blockIdx.x * kPredWaves + w; seg < n_seg; seg += gridDim.x * kPredWaves) {
         const uint32_t r = seg * kSeg + lane;
-        const bool ok = r < g.n_edges;
-        float f[kFeat];
-        if (ok) {
-            root_features(g, t, dsat, r, f);
-        } else {
-#pragma unroll
-            for (int k = 0; k < kFeat; ++k) f[k] = 0.f;
+        uint4 a = make_uint4(0, 0, 0, 0), b = a;
+        if (r < n_roots) {
+            a = feats[2 * (size_t)r];
+            b = feats[2 * (size_t)r + 1];
         }
-        mlp_rows64(m, f, Xs[w], Hs[w], Ps[w], lane);
-        const bool live = ok && f[11] != 0.f;        // searched root (not a self-loop)
+        uint4 *row = reinterpret_cast<uint4 *>(Xs[w] + lane * 32);
+        row[0] = a;
+        row[1] = b;
+        row[2] = make_uint4(0, 0, 0, 0);
+        row[3] = make_uint4(0, 0, 0, 0);
+        wave_sync();
+        for (int tile = 0; tile < 4; ++tile) {
+            float out[4];
+            mlp_tile(m, Xs[w] + tile * 16 * 32, Hs[w], lane, out);
+            if ((lane & 15) == 0)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) Ps[w][tile * 16 + 4 * (lane >> 4) + q] = out[q];
+            wave_sync();
+        }
+        const bool live = (b.y >> 16) != 0;      // feature 11 (constant 1) is 0 for self-loops
         float c = live ? expf(fminf(fmaxf(Ps[w][lane], 0.f), 40.f)) : 0.f;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
@@ -272,14 +305,24 @@ __global__ void fill_u32(uint32_t *p, uint32_t n, uint32_t v) {
         p[i] = v;
 }
 
-// work: hist[kBins] | base[kBins] | fill[kBins] | split threshold (float bits) | ...
+// work: hist[kBins] | base[kBins] | fill[kBins] | ...
+// A segment is heavy when its predicted cost exceeds heavy_mult times the mean
+// segment cost; only heavy segments become items (and skip[] marks them), the
+// rest stay with the time-ordered queue.  A heavy segment above split_frac of
+// the total becomes one item per root.
+__device__ __forceinline__ bool is_heavy(float c, float total, uint32_t n_seg, float heavy_mult) {
+    return total > 0.f && c > heavy_mult * (total / (float)n_seg);
+}
+
 __global__ void bin_hist_kernel(const float *seg_cost, uint32_t n_seg, uint32_t n_roots,
-                                const float *total, float split_frac, uint32_t *work) {
-    const float split = *total * split_frac;
+                                const float *total, float heavy_mult, float split_frac,
+                                uint32_t *work) {
+    const float tot = *total, split = tot * split_frac;
     for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n_seg; s += gridDim.x * blockDim.x) {
         const float c = seg_cost[s];
+        if (!is_heavy(c, tot, n_seg, heavy_mult)) continue;
         const uint32_t nr = min((uint32_t)kSeg, n_roots - s * kSeg);
-        atomicAdd(&work[cost_bin(c)], (c > split && split > 0.f) ? nr : 1u);
+        atomicAdd(&work[cost_bin(c)], c > split ? nr : 1u);
     }
 }
 
@@ -296,16 +339,19 @@ __global__ void bin_scan_kernel(uint32_t *work, uint32_t *n_items) {
 }
 
 __global__ void bin_scatter_kernel(const float *seg_cost, uint32_t n_seg, uint32_t n_roots,
-                                   const float *total, float split_frac, uint32_t *work,
-                                   uint2 *items) {
-    const float split = *total * split_frac;
+                                   const float *total, float heavy_mult, float split_frac,
+                                   uint32_t *work, uint2 *items, uint8_t *skip) {
+    const float tot = *total, split = tot * split_frac;
     for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n_seg; s += gridDim.x * blockDim.x) {
         const float c = seg_cost[s];
+        const bool heavy = is_heavy(c, tot, n_seg, heavy_mult);
+        if (skip) skip[s] = heavy ? 1 : 0;
+        if (!heavy) continue;
         const int b = cost_bin(c);
         const uint32_t r0 = s * kSeg, nr = min((uint32_t)kSeg, n_roots - r0);
-        const bool heavy = c > split && split > 0.f;
-        const uint32_t pos = work[kBins + b] + atomicAdd(&work[2 * kBins + b], heavy ? nr : 1u);
-        if (heavy) {
+        const bool split1 = c > split;
+        const uint32_t pos = work[kBins + b] + atomicAdd(&work[2 * kBins + b], split1 ? nr : 1u);
+        if (split1) {
             for (uint32_t i = 0; i < nr; ++i) items[pos + i] = make_uint2(r0 + i, r0 + i + 1);
         } else {
             items[pos] = make_uint2(r0, r0 + nr);
@@ -584,25 +630,28 @@ hipError_t launch_predict_feats(const float *params, const float *feats, uint32_
 template <typename TT>
 hipError_t launch_predict_roots(const DevGraph<TT> &g, const DevTree &t, TT delta_sat,
                                 const float *params, float *seg_cost, float *total,
-                                hipStream_t st) {
+                                uint4 *feat_buf, hipStream_t st) {
     const uint32_t n_seg = (g.n_edges + kSeg - 1) / kSeg;
     if (n_seg == 0) return hipSuccess;
+    const uint32_t fb = std::min<uint32_t>((g.n_edges + 255) / 256, 8192);
+    hipLaunchKernelGGL(features_pack_kernel<TT>, dim3(fb), dim3(256), 0, st, g, t, delta_sat,
+                       feat_buf);
     const uint32_t blocks = std::min<uint32_t>((n_seg + kPredWaves - 1) / kPredWaves, 2048);
-    hipLaunchKernelGGL(predict_roots_kernel<TT>, dim3(blocks), dim3(kWave * kPredWaves), 0, st, g,
-                       t, delta_sat, params, seg_cost, n_seg, total);
+    hipLaunchKernelGGL(mlp_segments_kernel, dim3(blocks), dim3(kWave * kPredWaves), 0, st, params,
+                       feat_buf, g.n_edges, seg_cost, n_seg, total);
     return hipGetLastError();
 }
 
 hipError_t launch_bin(const float *seg_cost, uint32_t n_seg, uint32_t n_roots,
-                      const float *total, float split_frac, uint32_t *work, uint2 *items,
-                      uint32_t *n_items_out, hipStream_t st) {
+                      const float *total, float heavy_mult, float split_frac, uint32_t *work,
+                      uint2 *items, uint32_t *n_items_out, uint8_t *skip, hipStream_t st) {
     hipLaunchKernelGGL(fill_u32, dim3(1), dim3(256), 0, st, work, (uint32_t)kBinWords, 0u);
     const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>((n_seg + 255) / 256, 2048));
     hipLaunchKernelGGL(bin_hist_kernel, dim3(blocks), dim3(256), 0, st, seg_cost, n_seg, n_roots,
-                       total, split_frac, work);
+                       total, heavy_mult, split_frac, work);
     hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(64), 0, st, work, n_items_out);
     hipLaunchKernelGGL(bin_scatter_kernel, dim3(blocks), dim3(256), 0, st, seg_cost, n_seg,
-                       n_roots, total, split_frac, work, items);
+                       n_roots, total, heavy_mult, split_frac, work, items, skip);
     return hipGetLastError();
 }
 
@@ -633,9 +682,9 @@ template hipError_t launch_features<uint64_t>(const DevGraph<uint64_t> &, const 
                                               const uint32_t *, uint32_t, float *, hipStream_t);
 template hipError_t launch_predict_roots<uint32_t>(const DevGraph<uint32_t> &, const DevTree &,
                                                    uint32_t, const float *, float *, float *,
-                                                   hipStream_t);
+                                                   uint4 *, hipStream_t);
 template hipError_t launch_predict_roots<uint64_t>(const DevGraph<uint64_t> &, const DevTree &,
                                                    uint64_t, const float *, float *, float *,
-                                                   hipStream_t);
+                                                   uint4 *, hipStream_t);
 
 }  // namespace mg

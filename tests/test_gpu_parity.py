@@ -264,6 +264,32 @@ def test_batch_equals_single_counts_and_oracle(gpu):
         b.close()
 
 
+@pytest.mark.parametrize("depth", [1, 2, 3, 5])
+def test_batch_every_depth(depth):
+    """Batches whose deepest tree has 1, 2, 3 or 5 edges (each depth is its own
+    kernel instantiation with its own per-wave LDS layout)."""
+    rng = np.random.default_rng(30 + depth)
+    graphs, trees, want = [], [], []
+    for j in range(3):
+        n = int(rng.integers(6, 40))
+        s, d, t = tiny_graph(rng, n, int(rng.integers(200, 2500)), 400, self_loops=True)
+        ks = tuple(range(1, depth + 1))
+        ms = W.random_extension_motifs(6, ks, 6, 300 + 10 * depth + j)
+        if j == 0:
+            ms = ms + [tuple([(0, 1)] + [(1, 0), (0, 1)] * 2)[:depth]]
+        delta = int(rng.integers(10, 120))
+        og = OracleGraph(s, d, t, n)
+        graphs.append(api.Graph(s, d, t, n))
+        trees.append(api.Tree(ms, delta))
+        want.append(oracle_counts(og, ms, delta))
+    say("batch depth", depth)
+    b = api.Batch(graphs, trees, item_roots=64)
+    assert b.info()["depth"] == depth
+    for _ in range(2):
+        for a, w in zip(b.count(), want):
+            assert np.array_equal(a, w)
+
+
 def test_config1_full():
     wl = W.make_config(1)
     s, d, t, n = wl.graphs[0]
