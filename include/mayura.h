@@ -135,16 +135,21 @@ typedef struct {
     uint64_t *stats;          /* optional out, MG_NSTATS entries: search statistics
                                  (runs an instrumented kernel; not for timing) */
     int32_t sched;            /* MG_SCHED_PLAIN (default) or MG_SCHED_LEARNED */
-    int32_t leaf_scan;        /* windows up to this long whose children all end a
-                                 motif are counted by one lane: 0 = default (no
-                                 limit), < 0 = never (every window goes through
-                                 the wave-wide candidate expansion) */
+    int32_t leaf_scan;        /* windows whose children all end a motif are
+                                 counted without the candidate expansion: by one
+                                 lane when at most this long, by the whole wave
+                                 (one ballot per bound vertex) when longer.
+                                 0 = default (256), < 0 = never (every window goes
+                                 through the candidate expansion) */
     const struct mg_model *model;   /* cost model for MG_SCHED_LEARNED */
     uint64_t *root_cost;      /* optional out, n_edges entries indexed by root edge:
                                  1 + the candidate edges examined (window entries)
                                  in the search below that root, 0 for roots not
                                  searched; summed over motifs in per-motif mode.
                                  Runs an instrumented kernel; exclusive with stats. */
+    int32_t sample;           /* MG_SCHED_LEARNED: the model scores one root in
+                                 `sample` of every 64-root segment (a power of
+                                 two, 1..64; 0 = default 1) */
 } mg_count_opts;
 
 /* mg_count_opts.stats entries; every one is independent of the schedule */
@@ -162,8 +167,8 @@ typedef struct {
 #define MG_SCHED_LEARNED 1    /* an MLP predicts the cost of every 64-root
                                  segment; segments above 8x the mean run first,
                                  heaviest first (the costliest split into single
-                                 roots), then the rest in time order from one
-                                 queue (ignores chunk and queues) */
+                                 roots), then the rest in time order from the
+                                 root queues in 64-root chunks (ignores chunk) */
 
 /* Fill opts with the defaults (co-mining, all roots, null stream). */
 void mg_count_opts_init(mg_count_opts *opts);

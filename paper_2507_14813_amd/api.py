@@ -54,7 +54,7 @@ class CountOpts(ctypes.Structure):
                 ("elapsed_ms", ctypes.POINTER(ctypes.c_float)),
                 ("stats", ctypes.c_void_p), ("sched", ctypes.c_int32),
                 ("leaf_scan", ctypes.c_int32), ("model", ctypes.c_void_p),
-                ("root_cost", ctypes.c_void_p)]
+                ("root_cost", ctypes.c_void_p), ("sample", ctypes.c_int32)]
 
 
 STAT_NAMES = ("win_list", "win_all", "ent_list", "ent_all", "push", "credit", "roots")
@@ -263,12 +263,13 @@ class Tree:
 
 def count(graph: Graph, tree: Tree, mode="comine", roots=None, blocks=0, chunk=0,
           queues=0, stream=None, timed=False, stats=False, root_cost=False, model=None,
-          leaf_scan=0):
+          leaf_scan=0, sample=0):
     """Exact count per motif (``mg_count``), in the tree's motif order.
 
     ``mode``: "comine" (one search over the MG-Tree) or "per_motif" (one search
     per motif).  ``roots``: optional root positions (time order).  ``model``:
-    a ``Model`` selects the learned schedule.  Returns a
+    a ``Model`` selects the learned schedule (``sample``: it scores one root in
+    that many per 64-root segment, 0 = default).  Returns a
     uint64 array; with ``timed`` also the device milliseconds; with ``stats``
     also a dict of search statistics; with ``root_cost`` also the per-root
     cost log (uint64 per edge; both run instrumented kernels).
@@ -281,6 +282,7 @@ def count(graph: Graph, tree: Tree, mode="comine", roots=None, blocks=0, chunk=0
     o.chunk = int(chunk)
     o.queues = int(queues)
     o.leaf_scan = int(leaf_scan)
+    o.sample = int(sample)
     if model is not None:
         o.sched = 1
         o.model = model.handle.value

@@ -12,7 +12,7 @@ constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;
 constexpr int kQueues = 8;      // root queues, one per XCD
 constexpr int kQueueStride = 16;  // u64 words between queue heads (own cache line)
-constexpr uint32_t kLeafScanDefault = 0xffffffffu;   // every leaf-only window
+constexpr uint32_t kLeafScanDefault = 256;   // lane-counted leaf window limit
 
 // group direction: which adjacency list holds the candidates
 enum : int { kDirOut = 0, kDirIn = 1, kDirAll = 2 };
@@ -68,14 +68,21 @@ struct KParams {
     unsigned long long *stats;    // NULL, or kStats totals (zeroed before launch)
     unsigned long long *root_cost;  // NULL, or per root edge id: 1 + window entries
                                     // examined below that root (zeroed before launch)
-    const uint2 *items;           // NULL, or work items {first, end} of root positions,
-                                  // searched before the queues
+    const uint2 *items;           // NULL, or work items searched before the queues:
+                                  // {first, end} of root positions, or, with
+                                  // kItemSplit set in .y, {root, kItemSplit |
+                                  // part << 15 | nparts} (part < nparts < 2^15;
+                                  // p.roots NULL): one part of one root's search
     const uint32_t *n_items;      // device count of items (with items)
     const uint8_t *skip;          // NULL, or per 64-root segment: 1 = covered by the
-                                  // items (needs one queue and 64-root chunks)
-    uint32_t leaf_scan;           // windows up to this long whose children are all
-                                  // leaves are counted by one lane (0: never)
+                                  // items (needs 64-root chunks and roots NULL)
+    uint32_t leaf_scan;           // windows whose children are all leaves are counted
+                                  // without the candidate expansion: by one lane up
+                                  // to this long, by the whole wave when longer
+                                  // (0: never)
 };
+
+constexpr uint32_t kItemSplit = 0x80000000u;
 
 // search statistics (schedule independent), filled when KParams::stats is set
 enum : int {

@@ -65,32 +65,93 @@ __device__ __forceinline__ uint32_t credit_child(uint32_t word, uint32_t c,
 
 // Counts a leaf-only window [l0, l0 + len) of one adjacency list for the
 // partial match with bound vertices ph[0..nvp): each entry reaches the child
-// of the bound vertex it hits, or the new-vertex child.  Returns the credits.
+// of the bound vertex it hits, or the new-vertex child.  The bound vertices
+// are distinct, so an entry hits at most one of them: one equality count per
+// bound vertex, and the new-vertex count is what is left.  Returns the credits.
 template <typename TT, int SA>
 __device__ __forceinline__ uint32_t leaf_scan_window(const Entry<TT> *__restrict__ adj,
                                                      uint32_t l0, uint32_t len,
                                                      const int32_t (&ph)[SA], uint32_t nvp,
                                                      const uint4 ga, const uint4 gb,
                                                      unsigned long long *cnt) {
-    uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0, cn = 0;
-    auto tally = [&](int32_t v) {
-        int y = -1;
+    int32_t q[SA];
+    uint32_t c[SA];
 #pragma unroll
-        for (int s = 0; s < SA; ++s) y = ((uint32_t)s < nvp && ph[s] == v) ? s : y;
-        c0 += y == 0; c1 += y == 1; c2 += y == 2; c3 += y == 3; c4 += y == 4; c5 += y == 5;
-        cn += y < 0;
-    };
+    for (int s = 0; s < SA; ++s) {
+        q[s] = (uint32_t)s < nvp ? ph[s] : -1;   // graph vertex ids are >= 0
+        c[s] = 0;
+    }
     const Entry<TT> *e = adj + l0;
     uint32_t i = 0;
     for (; i + 4 <= len; i += 4) {
-        const int32_t v0 = e[i].v, v1 = e[i + 1].v, v2 = e[i + 2].v, v3 = e[i + 3].v;
-        tally(v0); tally(v1); tally(v2); tally(v3);
+        int32_t v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = e[i + j].v;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int s = 0; s < SA; ++s) c[s] += v[j] == q[s];
     }
-    for (; i < len; ++i) tally(e[i].v);
-    return credit_child(ga.y, c0, cnt) + credit_child(ga.z, c1, cnt) +
-           credit_child(ga.w, c2, cnt) + credit_child(gb.x, c3, cnt) +
-           credit_child(gb.y, c4, cnt) + credit_child(gb.z, c5, cnt) +
-           credit_child(gb.w, cn, cnt);
+    for (; i < len; ++i) {
+        const int32_t v = e[i].v;
+#pragma unroll
+        for (int s = 0; s < SA; ++s) c[s] += v == q[s];
+    }
+    const uint32_t words[6] = {ga.y, ga.z, ga.w, gb.x, gb.y, gb.z};
+    uint32_t hit = 0, got = 0;
+#pragma unroll
+    for (int s = 0; s < SA; ++s) {
+        hit += c[s];
+        got += credit_child(words[s], c[s], cnt);
+    }
+    return got + credit_child(gb.w, len - hit, cnt);
+}
+
+// Counts the leaf-only window [l0, l0 + len) of group g for buffered partial
+// match x with the whole wave, 64 entries per pass: one ballot per bound
+// vertex counts the entries that hit it, and the new-vertex child gets the
+// rest.  All arguments are wave-uniform.  Returns the credits on lane 0
+// (0 on the other lanes).
+template <typename TT, int SA, int CAP>
+__device__ __forceinline__ uint32_t leaf_scan_wave(const KParams<TT> &p,
+                                                   const int32_t (&phi)[SA][CAP], uint32_t x,
+                                                   uint32_t g, uint32_t l0, uint32_t len,
+                                                   const int lane, unsigned long long *cnt) {
+    const uint4 ga = p.tree.grp[2 * g], gb = p.tree.grp[2 * g + 1];
+    const uint32_t nvp = (ga.x >> 8) & 15;
+    const Entry<TT> *__restrict__ e =
+        ((ga.x & 15) == kDirOut ? p.g.out_adj : p.g.in_adj) + l0;
+    int32_t q[SA];
+    uint32_t c[SA];
+#pragma unroll
+    for (int s = 0; s < SA; ++s) {
+        q[s] = (uint32_t)s < nvp ? (int32_t)uniform((uint32_t)phi[s][x]) : -1;
+        c[s] = 0;
+    }
+    uint32_t i = 0;
+    for (; i + 4 * kWave <= len; i += 4 * kWave) {
+        int32_t v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = e[i + j * kWave + lane].v;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int s = 0; s < SA; ++s) c[s] += (uint32_t)__popcll(__ballot(v[j] == q[s]));
+    }
+    for (; i < len; i += kWave) {
+        const int32_t v = i + lane < len ? e[i + lane].v : -2;   // -2 matches no slot
+#pragma unroll
+        for (int s = 0; s < SA; ++s) c[s] += (uint32_t)__popcll(__ballot(v == q[s]));
+    }
+    if (lane != 0) return 0;
+    const uint32_t words[6] = {ga.y, ga.z, ga.w, gb.x, gb.y, gb.z};
+    uint32_t hit = 0, got = 0;
+#pragma unroll
+    for (int s = 0; s < SA; ++s) {
+        hit += c[s];
+        got += credit_child(words[s], c[s], cnt);
+    }
+    return got + credit_child(gb.w, len - hit, cnt);
 }
 
 // Partial matches with L motif edges matched.  Level 1 is the root batch:
@@ -106,6 +167,7 @@ struct LevelBuf {
     TT tprev[C];
     uint16_t node[C];      // internal trie node reached
     uint16_t pincl[C];     // inclusive prefix of child-group counts
+    uint8_t r1[C];         // slot of its root in the level-1 batch
     uint32_t root[R ? C : 1];
 };
 template <typename TT, bool R>
@@ -129,10 +191,20 @@ struct LevelChain<TT, D, R, D> {};
 // multiple of 16 bytes, so that per-wave blocks laid out back to back (with
 // 64-bit counters between them) keep those counters 8-byte aligned, as LDS
 // 64-bit atomics require.
+//
+// Root windows: for each root of the level-1 batch, the windows it found in
+// out(a), in(a), out(b), in(b) (index anchor * 2 + direction; lo > hi when not
+// found yet).  A deeper partial match of that root reads a window of the same
+// list with t_prev < t <= t_first + delta, t_prev > t_first: it starts inside
+// the root's window and ends where it ends, so a bisection over the root's
+// window replaces a bisection over the whole list and the search for the end.
 template <typename TT, int D, bool R>
 struct alignas(16) WaveLds {
+    static constexpr int H = D > 2 ? 4 : 1;
     uint8_t src[kWave];           // window compaction: lane holding the k-th window
     uint8_t flag[kWave];          // window-end marks of one pass
+    uint32_t hlo[H][kWave];       // root windows (used when D > 2)
+    uint32_t hhi[H][kWave];
     LevelChain<TT, D, R, 1> lv;
 };
 
@@ -153,16 +225,31 @@ struct Stats {
 };
 
 // MODE: 0 plain search, 1 with search statistics, 2 with the per-root cost log
+// At level 1 with nparts > 1 (one buffered root), only part `part` of the
+// root's candidates is expanded: [T * part / nparts, T * (part + 1) / nparts)
+// of its T candidates in window order, so that the parts of one root
+// partition its search exactly; windows that a single lane counts, and the
+// root's window statistics, belong to part 0.
 template <typename TT, int D, int MODE, int L>
 __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, MODE == 2> &W,
                                           unsigned long long *cnt, const int lane,
-                                          const uint32_t nA, Stats &st) {
+                                          const uint32_t nA, Stats &st, const uint32_t part = 0,
+                                          const uint32_t nparts = 1) {
     constexpr bool STATS = MODE == 1, LOG = MODE == 2;
     LevelBuf<TT, L, LOG> &A = lvl<L>(W.lv);
     constexpr int SA = LevelBuf<TT, L, LOG>::S;
     const uint32_t *__restrict__ inode = p.tree.inode;
     const uint4 *__restrict__ grp = p.tree.grp;
     const uint64_t le_mask = (lane == 63) ? ~0ull : ((2ull << lane) - 1);
+
+    if constexpr (L == 1 && D > 2) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            W.hlo[k][lane] = 1u;
+            W.hhi[k][lane] = 0u;
+        }
+        wave_sync();
+    }
 
     // child groups per buffered partial match -> inclusive prefix (at the
     // root level every entry has the root's groups)
@@ -222,38 +309,60 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                     const TT thi = sat_add(A.tfirst[lo], p.delta_sat);
                     uint32_t b, e, sh;
                     const TT *ta;
+                    bool hinted = false;
                     if (dir == kDirAll) {
                         b = 0; e = p.g.n_edges; ta = p.g.gt; sh = 0;
                         all = true;
                     } else {
-                        const int32_t a = A.phi[anc][lo];
-                        const uint32_t *off = dir == kDirOut ? p.g.out_off : p.g.in_off;
-                        b = off[a]; e = off[a + 1];
                         ta = times_of(dir == kDirOut ? p.g.out_adj : p.g.in_adj);
                         sh = 1;
+                        if constexpr (L > 1 && D > 2) {
+                            if (anc < 2) {
+                                const uint32_t k = (uint32_t)anc * 2u + (uint32_t)dir;
+                                const uint32_t r1 = A.r1[lo];
+                                b = W.hlo[k][r1];
+                                e = W.hhi[k][r1];
+                                hinted = b <= e;
+                            }
+                        }
+                        if (!hinted) {
+                            const int32_t a = A.phi[anc][lo];
+                            const uint32_t *off = dir == kDirOut ? p.g.out_off : p.g.in_off;
+                            b = off[a]; e = off[a + 1];
+                        }
                     }
                     l0 = first_greater(ta, sh, b, e, tp);
-                    len = gallop_greater(ta, sh, l0, e, thi) - l0;
+                    len = (hinted ? e : gallop_greater(ta, sh, l0, e, thi)) - l0;
+                    if constexpr (L == 1 && D > 2) {
+                        if (!all && anc < 2) {
+                            const uint32_t k = (uint32_t)anc * 2u + (uint32_t)dir;
+                            W.hlo[k][lo] = l0;
+                            W.hhi[k][lo] = l0 + len;
+                        }
+                    }
                 }
                 // take the longest prefix of pairs whose candidates stay below 2^31
                 const uint64_t incl64 = incl_scan64((uint64_t)len, lane);
                 const bool take = pi < P && incl64 <= kChunkLimit;
                 pc += uniform((uint32_t)__popcll(__ballot(take)));
+                const bool own = part == 0;   // this part keeps the per-window work
                 if constexpr (STATS) {
-                    if (take) {
+                    if (take && own) {
                         st.v[all ? kStatWinAll : kStatWinList] += 1;
                         st.v[all ? kStatEntAll : kStatEntList] += len;
                     }
                 }
                 if constexpr (LOG) {
-                    if (take && len > 0)
+                    if (take && own && len > 0)
                         atomicAdd(&p.root_cost[A.root[x]], (unsigned long long)len);
                 }
-                // a short window whose children are all leaves is counted by
-                // its own lane: independent loads, counts kept per child
-                bool scanned = false;
-                if (take && len > 0 && len <= p.leaf_scan && ((hdr >> 12) & 1)) {
-                    scanned = true;
+                // a window whose children are all leaves is counted without
+                // the candidate expansion: a short one by its own lane, a long
+                // one by the whole wave
+                const bool leaf = take && len > 0 && p.leaf_scan && ((hdr >> 12) & 1);
+                const bool scanned = leaf && len <= p.leaf_scan;
+                const bool coop = leaf && len > p.leaf_scan;
+                if (scanned && own) {
                     int32_t ph[SA];
 #pragma unroll
                     for (int s = 0; s < SA; ++s) ph[s] = A.phi[s][x];
@@ -262,10 +371,18 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                         (hdr >> 8) & 15, grp[2 * g], grp[2 * g + 1], cnt);
                     if constexpr (STATS) st.v[kStatCredit] += c;
                 }
+                for (uint64_t cm = __ballot(coop && own); cm; cm &= cm - 1) {
+                    const int src = (int)__builtin_ctzll(cm);
+                    const uint32_t c = leaf_scan_wave<TT, SA>(
+                        p, A.phi, __builtin_amdgcn_readlane(x, src),
+                        __builtin_amdgcn_readlane(g, src), __builtin_amdgcn_readlane(l0, src),
+                        __builtin_amdgcn_readlane(len, src), lane, cnt);
+                    if constexpr (STATS) st.v[kStatCredit] += c;
+                }
                 // compact the other non-empty windows into lanes 0..nw-1; their
-                // candidate ranges are numbered without the lane-counted ones
+                // candidate ranges are numbered without the leaf-counted ones
                 // (the chunk total stays below the limit checked above)
-                const bool keep = take && len > 0 && !scanned;
+                const bool keep = take && len > 0 && !leaf;
                 const uint32_t lk = keep ? len : 0u;
                 const uint32_t incl = incl_scan32(lk, lane);
                 const uint64_t km = __ballot(keep);
@@ -281,6 +398,11 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                 if ((uint32_t)lane >= nw) wrec = make_uint4(0, 0, 0, 0);
                 T = nw ? uniform(__shfl(wrec.w, (int)nw - 1)) : 0u;
                 cc = 0;
+                if (L == 1 && nparts > 1) {
+                    // one root, so every window fits this one chunk
+                    cc = (uint32_t)(((uint64_t)T * part) / nparts);
+                    T = (uint32_t)(((uint64_t)T * (part + 1)) / nparts);
+                }
             }
         }
         if (!done && cc < T) {
@@ -364,6 +486,8 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                     B.tfirst[slot] = A.tfirst[ox];
                     B.tprev[slot] = tnew;
                     B.node[slot] = (uint16_t)(cw & 0xffffu);
+                    if constexpr (L == 1) B.r1[slot] = (uint8_t)ox;
+                    else B.r1[slot] = A.r1[ox];
                     if constexpr (LOG) B.root[slot] = A.root[ox];
                     if constexpr (STATS) st.v[kStatPush] += 1;
                 }
@@ -380,6 +504,38 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
             }
         }
         if (done) break;
+    }
+}
+
+// Search from part `part` of `nparts` of the root at position r (an edge id:
+// split items come only with p.roots NULL); part 0 credits the root itself.
+template <typename TT, int D, int MODE>
+__device__ __forceinline__ void process_root_part(const KParams<TT> &p,
+                                                  WaveLds<TT, D, MODE == 2> &W,
+                                                  unsigned long long *cnt, const int lane,
+                                                  const uint32_t r, const uint32_t part,
+                                                  const uint32_t nparts, Stats &st) {
+    constexpr bool STATS = MODE == 1, LOG = MODE == 2;
+    const int32_t s = p.g.gsrc[r], d = p.g.gdst[r];
+    if (s == d) return;
+    if (part == 0) {
+        if (p.tree.root_q >= 0 && lane == 0) atomicAdd(&cnt[p.tree.root_q], 1ull);
+        if constexpr (STATS) st.v[kStatRoots] += lane == 0 ? 1 : 0;
+        if constexpr (LOG) {
+            if (lane == 0) atomicAdd(&p.root_cost[r], 1ull);
+        }
+    }
+    if constexpr (D > 1) {
+        LevelBuf<TT, 1, LOG> &A = lvl<1>(W.lv);
+        if (lane == 0) {
+            A.phi[0][0] = s;
+            A.phi[1][0] = d;
+            A.tfirst[0] = p.g.gt[r];
+            if constexpr (LOG) A.root[0] = r;
+        }
+        wave_sync();
+        run_level<TT, D, MODE, 1>(p, W, cnt, lane, 1u, st, part, nparts);
+        wave_sync();
     }
 }
 
@@ -456,7 +612,12 @@ comine_kernel(const KParams<TT> p) {
             it = __shfl(it, 0);
             if (it >= n_items) break;
             const uint2 item = p.items[uniform((uint32_t)it)];
-            process_roots<TT, D, MODE>(p, W, cnt, lane, uniform(item.x), uniform(item.y), st);
+            const uint32_t iy = uniform(item.y);
+            if (iy & kItemSplit)
+                process_root_part<TT, D, MODE>(p, W, cnt, lane, uniform(item.x),
+                                               (iy >> 15) & 0x7fffu, iy & 0x7fffu, st);
+            else
+                process_roots<TT, D, MODE>(p, W, cnt, lane, uniform(item.x), iy, st);
         }
     }
     // workgroups are dispatched to the XCDs round-robin: start on this XCD's
@@ -465,8 +626,12 @@ comine_kernel(const KParams<TT> p) {
     const uint32_t home = blockIdx.x % nq;
     for (uint32_t qi = 0; qi < nq; ++qi) {
         const uint32_t q = (home + qi) % nq;
-        const uint32_t qbeg = (uint32_t)(((uint64_t)p.n_roots * q) / nq);
-        const uint32_t qend = (uint32_t)(((uint64_t)p.n_roots * (q + 1)) / nq);
+        // queue boundaries on multiples of 64 roots, so that 64-root chunks
+        // are the scheduler's segments
+        const uint32_t qbeg = min(p.n_roots, (uint32_t)(((uint64_t)p.n_roots * q) / nq + 63) & ~63u);
+        const uint32_t qend =
+            q + 1 == nq ? p.n_roots
+                        : min(p.n_roots, (uint32_t)(((uint64_t)p.n_roots * (q + 1)) / nq + 63) & ~63u);
         for (;;) {
             unsigned long long got = 0;
             if (lane == 0) got = atomicAdd(&p.queues[q * kQueueStride], (unsigned long long)p.chunk);

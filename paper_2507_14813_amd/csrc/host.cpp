@@ -22,6 +22,10 @@
 using mg::kVMax;
 using mg::kKMax;
 // kQueues root-queue heads plus one work-item queue head
+// the learned schedule predicts the cost of one root in this many per segment
+constexpr uint32_t kSampleDefault = 1;
+// most items one root's search is split into by the learned schedule
+constexpr uint32_t kRootParts = 16;
 constexpr size_t kQueueBytes = sizeof(unsigned long long) * (mg::kQueues + 1) * mg::kQueueStride;
 
 namespace {
@@ -373,7 +377,7 @@ int upload_tree(mg_tree *tr, int device, hipStream_t st) {
 // One launch of the co-mining kernel over a tree; counts land in d_counts.
 template <typename TT>
 int learned_search(const mg_graph *g, mg_tree *tr, const mg_model *model,
-                   const mg::KParams<TT> &base, int blocks, hipStream_t st);
+                   const mg::KParams<TT> &base, int blocks, uint32_t stride, hipStream_t st);
 
 template <typename TT>
 int launch_tree(const mg_graph *g, mg_tree *tr, const uint32_t *d_roots, uint32_t n_roots,
@@ -419,7 +423,8 @@ int launch_tree(const mg_graph *g, mg_tree *tr, const uint32_t *d_roots, uint32_
         HIP_TRY(hipEventRecord(e0, st));
     }
     if (n_roots > 0 && o.sched == MG_SCHED_LEARNED) {
-        int rc = learned_search<TT>(g, tr, o.model, p, o.blocks, st);
+        int rc = learned_search<TT>(g, tr, o.model, p, o.blocks,
+                                    o.sample > 0 ? (uint32_t)o.sample : kSampleDefault, st);
         if (rc) return rc;
     } else if (n_roots > 0) {
         hipError_t e = mg::launch_comine<TT>(p, o.blocks, st);
@@ -500,7 +505,7 @@ TT delta_sat(int64_t delta) {
 // item-driven search kernel.
 template <typename TT>
 int learned_search(const mg_graph *g, mg_tree *tr, const mg_model *model,
-                   const mg::KParams<TT> &base, int blocks, hipStream_t st) {
+                   const mg::KParams<TT> &base, int blocks, uint32_t stride, hipStream_t st) {
     const uint32_t E = (uint32_t)g->E;
     const uint32_t n_seg = (E + mg::kSeg - 1) / mg::kSeg;
     DevBuf d;
@@ -509,7 +514,7 @@ int learned_search(const mg_graph *g, mg_tree *tr, const mg_model *model,
     const size_t off_nitems = off_work + 4 * (size_t)mg::kBinWords;
     const size_t off_items = (off_nitems + 16 + 15) & ~(size_t)15;
     const size_t off_feat = (off_items + 8 * (size_t)std::max<uint32_t>(E, 1) + 15) & ~(size_t)15;
-    const size_t off_skip = off_feat + 32 * (size_t)std::max<uint32_t>(E, 1);
+    const size_t off_skip = off_feat + 32 * (size_t)std::max<uint32_t>((E + stride - 1) / stride, 1);
     int rc = dev_alloc(d, off_skip + n_seg + 16, (void *)st);
     if (rc) return rc;
     struct G { DevBuf *b; ~G() { dev_free(*b); } } guard{&d};
@@ -522,21 +527,21 @@ int learned_search(const mg_graph *g, mg_tree *tr, const mg_model *model,
     hipError_t e = mg::launch_fill_f32_zero(total, 1, st);
     if (e == hipSuccess)
         e = mg::launch_predict_roots<TT>(base.g, base.tree, base.delta_sat,
-                                         (const float *)model->params.ptr, seg_cost, total, feat,
-                                         st);
+                                         (const float *)model->params.ptr, stride, seg_cost, total,
+                                         feat, st);
     // segments predicted at more than 8x the mean go first (one root per item
-    // above ~1/(4 * resident waves) of the total); the rest keep time order
+    // above ~1/(4 * resident waves) of the total, heavy roots in up to
+    // kRootParts parts); the rest keep time order
     if (e == hipSuccess)
-        e = mg::launch_bin(seg_cost, n_seg, E, total, 8.0f, 1.0f / 32768.0f, work, items, n_items,
-                           skip, st);
+        e = mg::launch_bin(seg_cost, n_seg, E, total, 8.0f, 1.0f / 32768.0f, kRootParts, work,
+                           items, std::max<uint32_t>(E, 1), n_items, skip, st);
     if (e != hipSuccess) return fail(MG_EDEVICE, "learned schedule failed: %s", hipGetErrorString(e));
     mg::KParams<TT> p = base;
     p.items = items;
     p.n_items = n_items;
     p.skip = skip;
     p.roots = nullptr;
-    p.n_queues = 1;          // 64-root chunks stay aligned with the segments
-    p.chunk = mg::kSeg;
+    p.chunk = mg::kSeg;      // one chunk is one segment
     e = mg::launch_comine<TT>(p, blocks, st);
     if (e != hipSuccess) return fail(MG_EDEVICE, "co-mining launch failed: %s", hipGetErrorString(e));
     // the buffer is released after the caller synchronises the stream
@@ -646,7 +651,8 @@ int predict_job_segments(const mg_graph *g, mg_tree *tr, const mg_model *m, floa
     hipError_t e = mg::launch_fill_f32_zero(d_total, 1, st);
     if (e == hipSuccess)
         e = mg::launch_predict_roots<TT>(dev_graph<TT>(g), dev_tree(tr), delta_sat<TT>(tr->delta),
-                                         (const float *)m->params.ptr, d_seg, d_total, d_feat, st);
+                                         (const float *)m->params.ptr, kSampleDefault, d_seg,
+                                         d_total, d_feat, st);
     if (e != hipSuccess) return fail(MG_EDEVICE, "cost prediction failed: %s", hipGetErrorString(e));
     return MG_OK;
 }
@@ -661,7 +667,8 @@ int learned_items(mg_batch *b, const mg_model *m, hipStream_t st) {
         if (!n_seg) continue;
         DevBuf d;
         const size_t off_feat = (4 * (size_t)n_seg + 16 + 15) & ~(size_t)15;
-        int rc = dev_alloc(d, off_feat + 32 * (size_t)E, (void *)st);
+        int rc = dev_alloc(d, off_feat + 32 * (size_t)((E + kSampleDefault - 1) / kSampleDefault),
+                           (void *)st);
         if (rc) return rc;
         struct G { DevBuf *b; ~G() { dev_free(*b); } } guard{&d};
         float *d_seg = (float *)d.ptr, *d_total = d_seg + n_seg;
@@ -1207,6 +1214,8 @@ int mg_count(const mg_graph *g, const mg_tree *tr_c, const mg_count_opts *opts,
         if (o.sched == MG_SCHED_LEARNED) {
             if (!o.model) return fail(MG_EINVAL, "the learned schedule needs a model");
             if (o.roots) return fail(MG_EINVAL, "the learned schedule searches every root");
+            if (o.sample < 0 || o.sample > mg::kSeg || (o.sample & (o.sample - 1)))
+                return fail(MG_EINVAL, "sample must be 0 or a power of two up to %d", mg::kSeg);
             if (o.model->device != g->device) return fail(MG_EINVAL, "model on another device");
         }
         int dev = 0;

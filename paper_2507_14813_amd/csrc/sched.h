@@ -35,26 +35,31 @@ hipError_t launch_features(const DevGraph<TT> &g, const DevTree &t, TT delta_sat
 hipError_t launch_predict_feats(const float *params, const float *feats, uint32_t n, float *out,
                                 hipStream_t st);
 
-// Features (into feat_buf: 32 bytes per root edge) then the MLP for every
-// root edge; per 64-root segment writes the sum of exp(prediction) (predicted
-// cost) to seg_cost[n_edges / 64 rounded up] and adds every segment to *total
-// (zeroed by the caller).
+// Features (into feat_buf: 32 bytes per sampled root) then the MLP for one
+// root edge in every `stride` (a power of two, 1..64: roots 0, stride, ...);
+// per 64-root segment writes stride times the sum of exp(prediction) over its
+// sampled roots (predicted cost) to seg_cost[n_edges / 64 rounded up] and adds
+// every segment to *total (zeroed by the caller).
 template <typename TT>
 hipError_t launch_predict_roots(const DevGraph<TT> &g, const DevTree &t, TT delta_sat,
-                                const float *params, float *seg_cost, float *total,
-                                uint4 *feat_buf, hipStream_t st);
+                                const float *params, uint32_t stride, float *seg_cost,
+                                float *total, uint4 *feat_buf, hipStream_t st);
 
 // Binning: segments predicted to cost more than heavy_mult times the mean
-// segment become work items {begin, end} (root ranges), heaviest cost bin
+// segment become work items (root ranges {begin, end}), heaviest cost bin
 // first, and are flagged in skip[n_seg] (when skip is not NULL); a heavy
-// segment costlier than split_frac * (*total) becomes one item per root.
-// work: scratch of kBinWords u32 (zeroed here); items: capacity n_roots;
+// segment costlier than split_frac * (*total) becomes one item per root, and
+// a root of it whose share is still above that becomes up to max_parts
+// (1 .. 2^15 - 1) split items {root, kItemSplit | part << 15 | parts}.  When
+// the parts would need more than cap (>= n_roots) items, no root is split.
+// work: scratch of kBinWords u32 (zeroed here); items: capacity cap;
 // n_items_out: device u32.  heavy_mult = 0 makes every segment an item.
 constexpr int kBins = 48;
-constexpr int kBinWords = 3 * kBins + 4;
+constexpr int kBinWords = 4 * kBins + 4;
 hipError_t launch_bin(const float *seg_cost, uint32_t n_seg, uint32_t n_roots, const float *total,
-                      float heavy_mult, float split_frac, uint32_t *work, uint2 *items,
-                      uint32_t *n_items_out, uint8_t *skip, hipStream_t st);
+                      float heavy_mult, float split_frac, uint32_t max_parts, uint32_t *work,
+                      uint2 *items, uint32_t cap, uint32_t *n_items_out, uint8_t *skip,
+                      hipStream_t st);
 
 // p[0..n) = 0 with a kernel
 hipError_t launch_fill_f32_zero(float *p, uint32_t n, hipStream_t st);

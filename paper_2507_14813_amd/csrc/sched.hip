@@ -227,14 +227,17 @@ predict_feats_kernel(const float *P, const float *feats, uint32_t n, float *out)
     }
 }
 
-// Features of every root as 16 BF16 values (two 16-byte words per root).
+// Features of every stride-th root (roots 0, stride, 2*stride, ...) as 16
+// BF16 values, two 16-byte words per sampled root.
 template <typename TT>
 __global__ void __launch_bounds__(256)
-features_pack_kernel(const DevGraph<TT> g, const DevTree t, TT dsat, uint4 *out) {
-    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < g.n_edges;
-         r += gridDim.x * blockDim.x) {
+features_pack_kernel(const DevGraph<TT> g, const DevTree t, TT dsat, uint32_t stride,
+                     uint4 *out) {
+    const uint32_t n_rows = (g.n_edges + stride - 1) / stride;
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n_rows;
+         j += gridDim.x * blockDim.x) {
         float f[kFeat];
-        root_features(g, t, dsat, r, f);
+        root_features(g, t, dsat, j * stride, f);
         uint4 a, b;
         a.x = f2bf(f[0]) | ((uint32_t)f2bf(f[1]) << 16);
         a.y = f2bf(f[2]) | ((uint32_t)f2bf(f[3]) << 16);
@@ -244,30 +247,35 @@ features_pack_kernel(const DevGraph<TT> g, const DevTree t, TT dsat, uint4 *out)
         b.y = f2bf(f[10]) | ((uint32_t)f2bf(f[11]) << 16);
         b.z = f2bf(f[12]) | ((uint32_t)f2bf(f[13]) << 16);
         b.w = f2bf(f[14]) | ((uint32_t)f2bf(f[15]) << 16);
-        out[2 * (size_t)r] = a;
-        out[2 * (size_t)r + 1] = b;
+        out[2 * (size_t)j] = a;
+        out[2 * (size_t)j + 1] = b;
     }
 }
 
-// MLP over packed features, one 64-root segment per wave step: writes the
-// segment's predicted cost (sum of exp(prediction) over searched roots) and
-// adds it to *total.
+// MLP over the packed features of sampled roots, 64 rows per wave step (stride
+// segments of 64 / stride rows each): writes each segment's predicted cost,
+// stride times the sum of exp(prediction) over its sampled searched roots, and
+// adds the segment costs to *total.
 __global__ void __launch_bounds__(kWave * kPredWaves)
-mlp_segments_kernel(const float *P, const uint4 *feats, uint32_t n_roots, float *seg_cost,
-                    uint32_t n_seg, float *total) {
+mlp_segments_kernel(const float *P, const uint4 *feats, uint32_t n_roots, uint32_t stride,
+                    float *seg_cost, uint32_t n_seg, float *total) {
     __shared__ __align__(16) uint16_t Xs[kPredWaves][64 * 32];
     __shared__ __align__(16) uint16_t Hs[kPredWaves][16 * kHid];
     __shared__ float Ps[kPredWaves][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t n_rows = (n_roots + stride - 1) / stride;
+    const uint32_t n_steps = (n_rows + kWave - 1) / kWave;
+    const uint32_t rps = kSeg / stride;            // rows per segment
     MlpReg m;
     load_mlp(P, m, lane);
     float tsum = 0.f;
-    for (uint32_t seg = blockIdx.x * kPredWaves + w; seg < n_seg; seg += gridDim.x * kPredWaves) {
-        const uint32_t r = seg * kSeg + lane;
+    for (uint32_t step = blockIdx.x * kPredWaves + w; step < n_steps;
+         step += gridDim.x * kPredWaves) {
+        const uint32_t j = step * kWave + lane;
         uint4 a = make_uint4(0, 0, 0, 0), b = a;
-        if (r < n_roots) {
-            a = feats[2 * (size_t)r];
-            b = feats[2 * (size_t)r + 1];
+        if (j < n_rows) {
+            a = feats[2 * (size_t)j];
+            b = feats[2 * (size_t)j + 1];
         }
         uint4 *row = reinterpret_cast<uint4 *>(Xs[w] + lane * 32);
         row[0] = a;
@@ -285,12 +293,17 @@ mlp_segments_kernel(const float *P, const uint4 *feats, uint32_t n_roots, float 
         }
         const bool live = (b.y >> 16) != 0;      // feature 11 (constant 1) is 0 for self-loops
         float c = live ? expf(fminf(fmaxf(Ps[w][lane], 0.f), 40.f)) : 0.f;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
-        if (lane == 0) seg_cost[seg] = c;
-        tsum += c;
+        for (uint32_t o = rps >> 1; o > 0; o >>= 1) c += __shfl_xor(c, (int)o);
+        c *= (float)stride;
+        const uint32_t seg = step * stride + (uint32_t)lane / rps;
+        if ((uint32_t)lane % rps == 0 && seg < n_seg) {
+            seg_cost[seg] = c;
+            tsum += c;
+        }
         wave_sync();
     }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) tsum += __shfl_xor(tsum, o);
     if (lane == 0 && tsum > 0.f) atomicAdd(total, tsum);
 }
 
@@ -305,33 +318,53 @@ __global__ void fill_u32(uint32_t *p, uint32_t n, uint32_t v) {
         p[i] = v;
 }
 
-// work: hist[kBins] | base[kBins] | fill[kBins] | ...
+// work: hist[kBins] | base[kBins] | fill[kBins] | hist1[kBins] | flag
 // A segment is heavy when its predicted cost exceeds heavy_mult times the mean
 // segment cost; only heavy segments become items (and skip[] marks them), the
 // rest stay with the time-ordered queue.  A heavy segment above split_frac of
-// the total becomes one item per root.
+// the total becomes one item per root, and each of its roots becomes up to
+// max_parts items (parts of the root's first-level candidates) when its share
+// of the segment is still above split_frac of the total.  If the parts would
+// overflow the item capacity, roots are not split (flag set).
 __device__ __forceinline__ bool is_heavy(float c, float total, uint32_t n_seg, float heavy_mult) {
     return total > 0.f && c > heavy_mult * (total / (float)n_seg);
 }
 
+__device__ __forceinline__ uint32_t root_parts(float c, uint32_t nr, float split,
+                                               uint32_t max_parts) {
+    const float k = ceilf(c / ((float)nr * split));
+    return k >= (float)max_parts ? max_parts : (k < 1.f ? 1u : (uint32_t)k);
+}
+
 __global__ void bin_hist_kernel(const float *seg_cost, uint32_t n_seg, uint32_t n_roots,
                                 const float *total, float heavy_mult, float split_frac,
-                                uint32_t *work) {
+                                uint32_t max_parts, uint32_t *work) {
     const float tot = *total, split = tot * split_frac;
     for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n_seg; s += gridDim.x * blockDim.x) {
         const float c = seg_cost[s];
         if (!is_heavy(c, tot, n_seg, heavy_mult)) continue;
         const uint32_t nr = min((uint32_t)kSeg, n_roots - s * kSeg);
-        atomicAdd(&work[cost_bin(c)], c > split ? nr : 1u);
+        const int b = cost_bin(c);
+        if (c > split) {
+            atomicAdd(&work[b], nr * root_parts(c, nr, split, max_parts));
+            atomicAdd(&work[3 * kBins + b], nr);
+        } else {
+            atomicAdd(&work[b], 1u);
+            atomicAdd(&work[3 * kBins + b], 1u);
+        }
     }
 }
 
-__global__ void bin_scan_kernel(uint32_t *work, uint32_t *n_items) {
+__global__ void bin_scan_kernel(uint32_t *work, uint32_t cap, uint32_t *n_items) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
+        uint64_t all = 0;
+        for (int b = 0; b < kBins; ++b) all += work[b];
+        const bool whole = all > cap;          // no root parts
+        work[4 * kBins] = whole ? 1u : 0u;
         uint32_t run = 0;
         for (int b = kBins - 1; b >= 0; --b) {   // heaviest bin first
             work[kBins + b] = run;
-            run += work[b];
+            run += work[(whole ? 3 * kBins : 0) + b];
             work[2 * kBins + b] = 0;
         }
         *n_items = run;
@@ -340,8 +373,10 @@ __global__ void bin_scan_kernel(uint32_t *work, uint32_t *n_items) {
 
 __global__ void bin_scatter_kernel(const float *seg_cost, uint32_t n_seg, uint32_t n_roots,
                                    const float *total, float heavy_mult, float split_frac,
-                                   uint32_t *work, uint2 *items, uint8_t *skip) {
+                                   uint32_t max_parts, uint32_t *work, uint2 *items,
+                                   uint8_t *skip) {
     const float tot = *total, split = tot * split_frac;
+    const uint32_t mp = work[4 * kBins] ? 1u : max_parts;
     for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n_seg; s += gridDim.x * blockDim.x) {
         const float c = seg_cost[s];
         const bool heavy = is_heavy(c, tot, n_seg, heavy_mult);
@@ -349,11 +384,16 @@ __global__ void bin_scatter_kernel(const float *seg_cost, uint32_t n_seg, uint32
         if (!heavy) continue;
         const int b = cost_bin(c);
         const uint32_t r0 = s * kSeg, nr = min((uint32_t)kSeg, n_roots - r0);
-        const bool split1 = c > split;
-        const uint32_t pos = work[kBins + b] + atomicAdd(&work[2 * kBins + b], split1 ? nr : 1u);
-        if (split1) {
-            for (uint32_t i = 0; i < nr; ++i) items[pos + i] = make_uint2(r0 + i, r0 + i + 1);
+        if (c > split) {
+            const uint32_t k = root_parts(c, nr, split, mp);
+            const uint32_t pos = work[kBins + b] + atomicAdd(&work[2 * kBins + b], nr * k);
+            for (uint32_t i = 0; i < nr; ++i)
+                for (uint32_t j = 0; j < k; ++j)
+                    items[pos + i * k + j] =
+                        k == 1 ? make_uint2(r0 + i, r0 + i + 1)
+                               : make_uint2(r0 + i, kItemSplit | (j << 15) | k);
         } else {
+            const uint32_t pos = work[kBins + b] + atomicAdd(&work[2 * kBins + b], 1u);
             items[pos] = make_uint2(r0, r0 + nr);
         }
     }
@@ -629,29 +669,35 @@ hipError_t launch_predict_feats(const float *params, const float *feats, uint32_
 
 template <typename TT>
 hipError_t launch_predict_roots(const DevGraph<TT> &g, const DevTree &t, TT delta_sat,
-                                const float *params, float *seg_cost, float *total,
-                                uint4 *feat_buf, hipStream_t st) {
+                                const float *params, uint32_t stride, float *seg_cost,
+                                float *total, uint4 *feat_buf, hipStream_t st) {
     const uint32_t n_seg = (g.n_edges + kSeg - 1) / kSeg;
     if (n_seg == 0) return hipSuccess;
-    const uint32_t fb = std::min<uint32_t>((g.n_edges + 255) / 256, 8192);
+    if (stride == 0 || stride > (uint32_t)kSeg || (stride & (stride - 1)))
+        return hipErrorInvalidValue;
+    const uint32_t n_rows = (g.n_edges + stride - 1) / stride;
+    const uint32_t fb = std::min<uint32_t>((n_rows + 255) / 256, 8192);
     hipLaunchKernelGGL(features_pack_kernel<TT>, dim3(fb), dim3(256), 0, st, g, t, delta_sat,
-                       feat_buf);
-    const uint32_t blocks = std::min<uint32_t>((n_seg + kPredWaves - 1) / kPredWaves, 2048);
+                       stride, feat_buf);
+    const uint32_t steps = (n_rows + kWave - 1) / kWave;
+    const uint32_t blocks = std::min<uint32_t>((steps + kPredWaves - 1) / kPredWaves, 2048);
     hipLaunchKernelGGL(mlp_segments_kernel, dim3(blocks), dim3(kWave * kPredWaves), 0, st, params,
-                       feat_buf, g.n_edges, seg_cost, n_seg, total);
+                       feat_buf, g.n_edges, stride, seg_cost, n_seg, total);
     return hipGetLastError();
 }
 
 hipError_t launch_bin(const float *seg_cost, uint32_t n_seg, uint32_t n_roots,
-                      const float *total, float heavy_mult, float split_frac, uint32_t *work,
-                      uint2 *items, uint32_t *n_items_out, uint8_t *skip, hipStream_t st) {
+                      const float *total, float heavy_mult, float split_frac, uint32_t max_parts,
+                      uint32_t *work, uint2 *items, uint32_t cap, uint32_t *n_items_out,
+                      uint8_t *skip, hipStream_t st) {
+    if (max_parts < 1 || max_parts >= (1u << 15) || cap < n_roots) return hipErrorInvalidValue;
     hipLaunchKernelGGL(fill_u32, dim3(1), dim3(256), 0, st, work, (uint32_t)kBinWords, 0u);
     const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>((n_seg + 255) / 256, 2048));
     hipLaunchKernelGGL(bin_hist_kernel, dim3(blocks), dim3(256), 0, st, seg_cost, n_seg, n_roots,
-                       total, heavy_mult, split_frac, work);
-    hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(64), 0, st, work, n_items_out);
+                       total, heavy_mult, split_frac, max_parts, work);
+    hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(64), 0, st, work, cap, n_items_out);
     hipLaunchKernelGGL(bin_scatter_kernel, dim3(blocks), dim3(256), 0, st, seg_cost, n_seg,
-                       n_roots, total, heavy_mult, split_frac, work, items, skip);
+                       n_roots, total, heavy_mult, split_frac, max_parts, work, items, skip);
     return hipGetLastError();
 }
 
@@ -681,10 +727,10 @@ template hipError_t launch_features<uint32_t>(const DevGraph<uint32_t> &, const 
 template hipError_t launch_features<uint64_t>(const DevGraph<uint64_t> &, const DevTree &, uint64_t,
                                               const uint32_t *, uint32_t, float *, hipStream_t);
 template hipError_t launch_predict_roots<uint32_t>(const DevGraph<uint32_t> &, const DevTree &,
-                                                   uint32_t, const float *, float *, float *,
-                                                   uint4 *, hipStream_t);
+                                                   uint32_t, const float *, uint32_t, float *,
+                                                   float *, uint4 *, hipStream_t);
 template hipError_t launch_predict_roots<uint64_t>(const DevGraph<uint64_t> &, const DevTree &,
-                                                   uint64_t, const float *, float *, float *,
-                                                   uint4 *, hipStream_t);
+                                                   uint64_t, const float *, uint32_t, float *,
+                                                   float *, uint4 *, hipStream_t);
 
 }  // namespace mg

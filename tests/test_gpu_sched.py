@@ -180,8 +180,9 @@ def test_learned_schedule_counts_are_exact():
     for delta in (15, 60):
         tr = api.Tree(ms, delta)
         want = np.array([og.count(x, delta) for x in ms], dtype=np.uint64)
-        say("learned schedule", delta)
-        assert np.array_equal(api.count(g, tr, model=m), want)
+        for sample in (0, 1, 4, 64):
+            say("learned schedule", delta, "sample", sample)
+            assert np.array_equal(api.count(g, tr, model=m, sample=sample), want)
         _, cost = api.count(g, tr, root_cost=True)
         f = api.root_features(g, tr)
         live = cost > 0
@@ -193,6 +194,9 @@ def test_learned_schedule_counts_are_exact():
     tr = api.Tree(wl.motif_sets[0], wl.deltas[0])
     say("learned schedule config-2 mini")
     assert np.array_equal(api.count(g, tr, model=m), api.count(g, tr))
+    for bad in (-1, 3, 128):
+        with pytest.raises(api.MayuraError):
+            api.count(g, tr, model=m, sample=bad)
 
 
 def test_learned_batch_counts_are_exact():
@@ -215,3 +219,53 @@ def test_learned_batch_counts_are_exact():
     for _ in range(3):
         for a, w in zip(b.count(), want):
             assert np.array_equal(a, w)
+
+
+def _steep_model(scale=40.0):
+    """A model whose prediction grows steeply with the root's whole-list window
+    count (feature 8), so that a few segments are predicted to carry most of
+    the cost and their roots are split into parts."""
+    m = api.Model(seed=0)
+    P = np.zeros_like(m.weights())
+    P[8 * 64 + 0] = 1.0                       # W1[8][0]
+    P[2048 + 64 + 0] = 1.0                    # W2[0][0]
+    P[2048 + 64 + 4096 + 64 + 0] = 1.0        # W3[0][0]
+    P[2048 + 64 + 2 * (4096 + 64)] = scale    # W4[0]
+    m.set_weights(P)
+    return m
+
+
+def test_learned_split_roots_are_exact():
+    """Heavy segments become per-root items and heavy roots become parts of
+    their first-level candidates: counts, search statistics and the per-root
+    cost log stay those of the plain schedule."""
+    rng = np.random.default_rng(12)
+    # a dense burst (600 edges in 30 time units) inside a sparse background:
+    # the burst's roots have long whole-list windows, the rest short ones
+    s1, d1, t1 = tiny_graph(rng, 40, 600, 30, self_loops=True)
+    s2, d2, t2 = tiny_graph(rng, 40, 6000, 200_000, self_loops=True)
+    s, d, t = np.concatenate([s1, s2]), np.concatenate([d1, d2]), np.concatenate([t1, t2 + 1000])
+    ms = W.random_extension_motifs(20, (2, 3, 4), 5, 21)
+    og = OracleGraph(s, d, t, 40)
+    g = api.Graph(s, d, t, 40)
+    m = _steep_model()
+    for delta in (20, 90):
+        tr = api.Tree(ms, delta)
+        # the schedule this model makes really splits roots
+        pred = m.predict(api.root_features(g, tr))
+        live = api.root_features(g, tr)[:, 11] > 0
+        c = np.where(live, np.exp(np.clip(pred, 0, 40)), 0.0)
+        seg = np.add.reduceat(c, np.arange(0, len(c), 64))
+        tot = seg.sum()
+        heavy = (seg > 8 * tot / len(seg)) & (seg > tot / 32768)
+        assert heavy.any() and (seg[heavy] / 64 > tot / 32768).any()
+        want = np.array([og.count(x, delta) for x in ms], dtype=np.uint64)
+        for sample in (1, 8):
+            say("split roots", delta, sample)
+            assert np.array_equal(api.count(g, tr, model=m, sample=sample), want)
+        _, st_plain = api.count(g, tr, stats=True)
+        _, st_learn = api.count(g, tr, stats=True, model=m, sample=1)
+        assert st_plain == st_learn
+        _, rc_plain = api.count(g, tr, root_cost=True)
+        _, rc_learn = api.count(g, tr, root_cost=True, model=m, sample=1)
+        assert np.array_equal(rc_plain, rc_learn)
