@@ -136,9 +136,10 @@ typedef struct {
                                  (runs an instrumented kernel; not for timing) */
     int32_t sched;            /* MG_SCHED_PLAIN (default) or MG_SCHED_LEARNED */
     int32_t leaf_scan;        /* windows whose children all end a motif are
-                                 counted without the candidate expansion: by one
-                                 lane when at most this long, by the whole wave
-                                 (one ballot per bound vertex) when longer.
+                                 counted without the candidate expansion, one
+                                 equality count per bound vertex: by the window's
+                                 own lane when at most this long, by the whole
+                                 wave (one ballot per bound vertex) when longer.
                                  0 = default (256), < 0 = never (every window goes
                                  through the candidate expansion) */
     const struct mg_model *model;   /* cost model for MG_SCHED_LEARNED */

@@ -47,6 +47,8 @@ template <typename TT>
 struct DevGraph {
     const int32_t *gsrc, *gdst;   // time-sorted edge list (all edges)
     const TT *gt;
+    const uint2 *gpos;            // per edge: its index in out_adj and in in_adj
+                                  // (self-loops: unused)
     const uint32_t *out_off;      // V+1
     const Entry<TT> *out_adj;     // out-lists: destination, time
     const uint32_t *in_off;
@@ -110,7 +112,9 @@ struct BatchJob {
     uint32_t count_off;           // first counter of this job in BatchParams::counts
 };
 struct BatchItem {
-    uint32_t job, begin, end, pad;   // roots [begin, end) of one job
+    uint32_t job, begin, end;   // roots [begin, end) of one job
+    uint32_t part;              // 0, or kItemSplit | part << 15 | nparts: that part
+                                // of the search from root `begin` (end = begin + 1)
 };
 template <typename TT>
 struct BatchParams {

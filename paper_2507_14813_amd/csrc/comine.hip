@@ -187,7 +187,7 @@ struct LevelChain {
 template <typename TT, int D, bool R>
 struct LevelChain<TT, D, R, D> {};
 
-// per-wave LDS: level buffers plus two 64-byte scratch tables.  Its size is a
+// per-wave LDS: level buffers plus small scratch tables.  Its size is a
 // multiple of 16 bytes, so that per-wave blocks laid out back to back (with
 // 64-bit counters between them) keep those counters 8-byte aligned, as LDS
 // 64-bit atomics require.
@@ -200,7 +200,7 @@ struct LevelChain<TT, D, R, D> {};
 // window replaces a bisection over the whole list and the search for the end.
 template <typename TT, int D, bool R>
 struct alignas(16) WaveLds {
-    static constexpr int H = D > 2 ? 4 : 1;
+    static constexpr int H = D > 1 ? 4 : 1;
     uint8_t src[kWave];           // window compaction: lane holding the k-th window
     uint8_t flag[kWave];          // window-end marks of one pass
     uint32_t hlo[H][kWave];       // root windows (used when D > 2)
@@ -212,6 +212,21 @@ static_assert(sizeof(WaveLds<uint32_t, 1, false>) % 16 == 0, "per-wave LDS block
 static_assert(sizeof(WaveLds<uint32_t, 3, false>) % 16 == 0, "per-wave LDS block size");
 static_assert(sizeof(WaveLds<uint32_t, 5, false>) % 16 == 0, "per-wave LDS block size");
 static_assert(sizeof(WaveLds<uint64_t, 5, true>) % 16 == 0, "per-wave LDS block size");
+
+// A new root in level-1 slot `slot`: its root windows are not found yet
+// (lo > hi), and the lo words of out(a) and in(b) hold where the search for
+// those windows starts, just after the root edge's own index (pos + 1 >= 1).
+template <typename TT, int D, bool R>
+__device__ __forceinline__ void set_root_slot(WaveLds<TT, D, R> &W, uint32_t slot, uint2 pos) {
+    W.hlo[0][slot] = pos.x + 1u;
+    W.hhi[0][slot] = 0u;
+    W.hlo[1][slot] = 1u;
+    W.hhi[1][slot] = 0u;
+    W.hlo[2][slot] = 1u;
+    W.hhi[2][slot] = 0u;
+    W.hlo[3][slot] = pos.y + 1u;
+    W.hhi[3][slot] = 0u;
+}
 
 template <int L, typename TT, int D, bool R, int M>
 __device__ __forceinline__ LevelBuf<TT, L, R> &lvl(LevelChain<TT, D, R, M> &c) {
@@ -242,14 +257,6 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
     const uint4 *__restrict__ grp = p.tree.grp;
     const uint64_t le_mask = (lane == 63) ? ~0ull : ((2ull << lane) - 1);
 
-    if constexpr (L == 1 && D > 2) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            W.hlo[k][lane] = 1u;
-            W.hhi[k][lane] = 0u;
-        }
-        wave_sync();
-    }
 
     // child groups per buffered partial match -> inclusive prefix (at the
     // root level every entry has the root's groups)
@@ -331,7 +338,16 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                             b = off[a]; e = off[a + 1];
                         }
                     }
-                    l0 = first_greater(ta, sh, b, e, tp);
+                    // a root's own edge sits in out(a) and in(b): their windows
+                    // start just after it (past entries with its time)
+                    bool after = false;
+                    if constexpr (L == 1) {
+                        if (!all && anc == dir) {
+                            b = W.hlo[3 * dir][lo];
+                            after = true;
+                        }
+                    }
+                    l0 = after ? gallop_greater(ta, sh, b, e, tp) : first_greater(ta, sh, b, e, tp);
                     len = (hinted ? e : gallop_greater(ta, sh, l0, e, thi)) - l0;
                     if constexpr (L == 1 && D > 2) {
                         if (!all && anc < 2) {
@@ -531,6 +547,7 @@ __device__ __forceinline__ void process_root_part(const KParams<TT> &p,
             A.phi[0][0] = s;
             A.phi[1][0] = d;
             A.tfirst[0] = p.g.gt[r];
+            set_root_slot(W, 0, p.g.gpos[r]);
             if constexpr (LOG) A.root[0] = r;
         }
         wave_sync();
@@ -573,6 +590,7 @@ __device__ __forceinline__ void process_roots(const KParams<TT> &p,
                 A.phi[0][slot] = s;
                 A.phi[1][slot] = d;
                 A.tfirst[slot] = p.g.gt[r];
+                set_root_slot(W, slot, p.g.gpos[r]);
                 if constexpr (LOG) A.root[slot] = r;
             }
             const uint32_t n1 = uniform((uint32_t)__popcll(m));
@@ -684,7 +702,12 @@ batch_kernel(const BatchParams<TT> bp) {
         const uint32_t nq = (uint32_t)p.tree.n_q;
         for (uint32_t i = (uint32_t)lane; i < nq; i += kWave) cnt[i] = 0;
         wave_sync();
-        process_roots<TT, D, 0>(p, W, cnt, lane, uniform(item.begin), uniform(item.end), st);
+        const uint32_t ip = uniform(item.part);
+        if (ip & kItemSplit)
+            process_root_part<TT, D, 0>(p, W, cnt, lane, uniform(item.begin), (ip >> 15) & 0x7fffu,
+                                        ip & 0x7fffu, st);
+        else
+            process_roots<TT, D, 0>(p, W, cnt, lane, uniform(item.begin), uniform(item.end), st);
         wave_sync();
         for (uint32_t i = (uint32_t)lane; i < nq; i += kWave)
             if (cnt[i]) atomicAdd(&bp.counts[job.count_off + i], cnt[i]);

@@ -103,10 +103,11 @@ struct mg_graph {
     int64_t t_min = 0, t_max = 0;
     int time_bytes = 4;
     int device = 0;
-    DevBuf gsrc, gdst, gt, out_off, out_adj, in_off, in_adj;
+    DevBuf gsrc, gdst, gt, gpos, out_off, out_adj, in_off, in_adj;
     int64_t device_bytes = 0;
     ~mg_graph() {
-        for (DevBuf *b : {&gsrc, &gdst, &gt, &out_off, &out_adj, &in_off, &in_adj}) dev_free(*b);
+        for (DevBuf *b : {&gsrc, &gdst, &gt, &gpos, &out_off, &out_adj, &in_off, &in_adj})
+            dev_free(*b);
     }
 };
 
@@ -128,10 +129,13 @@ int upload_graph(mg_graph *g, const std::vector<int32_t> &s, const std::vector<i
     for (int32_t v = 0; v < V; ++v) { oo[v + 1] += oo[v]; io[v + 1] += io[v]; }
     const uint32_t A = oo[V];
     std::vector<mg::Entry<TT>> oadj(A), iadj(A);
+    std::vector<uint32_t> pos(2 * (size_t)E, 0);   // per edge: index in out_adj, in in_adj
     {
         std::vector<uint32_t> po(oo.begin(), oo.end() - 1), pi(io.begin(), io.end() - 1);
         for (int64_t i = 0; i < E; ++i) {
             if (s[i] == d[i]) continue;
+            pos[2 * i] = po[s[i]];
+            pos[2 * i + 1] = pi[d[i]];
             mg::Entry<TT> &x = oadj[po[s[i]]++];
             std::memset(&x, 0, sizeof x);
             x.v = d[i]; x.t = rt[i];
@@ -144,6 +148,7 @@ int upload_graph(mg_graph *g, const std::vector<int32_t> &s, const std::vector<i
     Up ups[] = {
         {&g->gsrc, s.data(), sizeof(int32_t) * E}, {&g->gdst, d.data(), sizeof(int32_t) * E},
         {&g->gt, rt.data(), sizeof(TT) * E},
+        {&g->gpos, pos.data(), sizeof(uint32_t) * 2 * E},
         {&g->out_off, oo.data(), sizeof(uint32_t) * (V + 1)},
         {&g->out_adj, oadj.data(), sizeof(mg::Entry<TT>) * A},
         {&g->in_off, io.data(), sizeof(uint32_t) * (V + 1)},
@@ -380,19 +385,15 @@ int learned_search(const mg_graph *g, mg_tree *tr, const mg_model *model,
                    const mg::KParams<TT> &base, int blocks, uint32_t stride, hipStream_t st);
 
 template <typename TT>
+mg::DevGraph<TT> dev_graph(const mg_graph *g);
+
+template <typename TT>
 int launch_tree(const mg_graph *g, mg_tree *tr, const uint32_t *d_roots, uint32_t n_roots,
                 unsigned long long *d_queues, unsigned long long *d_counts,
                 unsigned long long *d_stats, unsigned long long *d_cost,
                 const mg_count_opts &o, hipStream_t st, float *ms) {
     mg::KParams<TT> p{};
-    p.g.gsrc = (const int32_t *)g->gsrc.ptr;
-    p.g.gdst = (const int32_t *)g->gdst.ptr;
-    p.g.gt = (const TT *)g->gt.ptr;
-    p.g.out_off = (const uint32_t *)g->out_off.ptr;
-    p.g.out_adj = (const mg::Entry<TT> *)g->out_adj.ptr;
-    p.g.in_off = (const uint32_t *)g->in_off.ptr;
-    p.g.in_adj = (const mg::Entry<TT> *)g->in_adj.ptr;
-    p.g.n_edges = (uint32_t)g->E;
+    p.g = dev_graph<TT>(g);
     p.tree.inode = (const uint32_t *)tr->d_node.ptr;
     p.tree.grp = (const uint4 *)tr->d_grp.ptr;
     p.tree.n_q = (int32_t)tr->distinct.size();
@@ -477,6 +478,7 @@ mg::DevGraph<TT> dev_graph(const mg_graph *g) {
     d.gsrc = (const int32_t *)g->gsrc.ptr;
     d.gdst = (const int32_t *)g->gdst.ptr;
     d.gt = (const TT *)g->gt.ptr;
+    d.gpos = (const uint2 *)g->gpos.ptr;
     d.out_off = (const uint32_t *)g->out_off.ptr;
     d.out_adj = (const mg::Entry<TT> *)g->out_adj.ptr;
     d.in_off = (const uint32_t *)g->in_off.ptr;
@@ -594,14 +596,7 @@ int upload_jobs(mg_batch *b, hipStream_t st) {
         mg_tree *tr = b->trees[j];
         mg::BatchJob<TT> &J = jobs[j];
         std::memset(&J, 0, sizeof J);
-        J.g.gsrc = (const int32_t *)g->gsrc.ptr;
-        J.g.gdst = (const int32_t *)g->gdst.ptr;
-        J.g.gt = (const TT *)g->gt.ptr;
-        J.g.out_off = (const uint32_t *)g->out_off.ptr;
-        J.g.out_adj = (const mg::Entry<TT> *)g->out_adj.ptr;
-        J.g.in_off = (const uint32_t *)g->in_off.ptr;
-        J.g.in_adj = (const mg::Entry<TT> *)g->in_adj.ptr;
-        J.g.n_edges = (uint32_t)g->E;
+        J.g = dev_graph<TT>(g);
         J.tree.inode = (const uint32_t *)tr->d_node.ptr;
         J.tree.grp = (const uint4 *)tr->d_grp.ptr;
         J.tree.n_q = (int32_t)tr->distinct.size();
@@ -642,9 +637,7 @@ int make_items(mg_batch *b, int32_t item_roots, hipStream_t st) {
     return MG_OK;
 }
 
-// Items from predicted costs: every job's 64-root segments, heaviest first
-// across the whole batch; a segment worth more than a quarter of one wave's
-// fair share of the predicted total is split into single roots.
+// Predicted segment costs of one job (learned_items orders the items).
 template <typename TT>
 int predict_job_segments(const mg_graph *g, mg_tree *tr, const mg_model *m, float *d_seg,
                          float *d_total, uint4 *d_feat, hipStream_t st) {
@@ -689,19 +682,45 @@ int learned_items(mg_batch *b, const mg_model *m, hipStream_t st) {
     int dev = 0, ncu = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    const double split = total / (4.0 * 32.0 * std::max(ncu, 1));   // ~32 resident waves per CU
+    // heavy segments (above 8x the mean) first, heaviest first; one root per
+    // item above a quarter of one wave's fair share (~32 resident waves per
+    // CU), a root still above that in up to kRootParts parts of its
+    // first-level candidates; then every other segment in job order (largest
+    // graph first) and time order, as the plain schedule runs them
+    const double split = total / (4.0 * 32.0 * std::max(ncu, 1));
+    const double heavy = segs.empty() ? 0.0 : 8.0 * total / (double)segs.size();
     std::vector<std::pair<float, mg::BatchItem>> it;
-    it.reserve(segs.size());
-    for (const Seg &sg : segs) {
-        if (sg.cost > split && sg.end - sg.first > 1) {
-            const float c = sg.cost / (float)(sg.end - sg.first);
-            for (uint32_t r = sg.first; r < sg.end; ++r) it.push_back({c, {sg.job, r, r + 1, 0u}});
+    std::vector<uint8_t> is_heavy(segs.size(), 0);
+    for (size_t i = 0; i < segs.size(); ++i) {
+        const Seg &sg = segs[i];
+        if (!(total > 0.0 && sg.cost > heavy)) continue;
+        is_heavy[i] = 1;
+        const uint32_t nr = sg.end - sg.first;
+        if (sg.cost > split && nr > 1) {
+            const double c = (double)sg.cost / nr;
+            const uint32_t k =
+                (uint32_t)std::min<double>(kRootParts, std::max(1.0, std::ceil(c / split)));
+            for (uint32_t r = sg.first; r < sg.end; ++r)
+                for (uint32_t q = 0; q < k; ++q)
+                    it.push_back({(float)(c / k), {sg.job, r, r + 1,
+                                                   k > 1 ? (mg::kItemSplit | (q << 15) | k) : 0u}});
         } else {
             it.push_back({sg.cost, {sg.job, sg.first, sg.end, 0u}});
         }
     }
     std::stable_sort(it.begin(), it.end(),
                      [](const auto &x, const auto &y) { return x.first > y.first; });
+    std::vector<uint32_t> order(b->graphs.size());
+    std::iota(order.begin(), order.end(), 0u);
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+        return b->graphs[x]->E > b->graphs[y]->E;
+    });
+    std::vector<size_t> seg0(b->graphs.size() + 1, 0);   // first segment of each job
+    for (const Seg &sg : segs) seg0[sg.job + 1]++;
+    for (size_t j = 0; j < b->graphs.size(); ++j) seg0[j + 1] += seg0[j];
+    for (uint32_t j : order)
+        for (size_t i = seg0[j]; i < seg0[j + 1]; ++i)
+            if (!is_heavy[i]) it.push_back({0.f, {j, segs[i].first, segs[i].end, 0u}});
     b->items.clear();
     for (auto &x : it) b->items.push_back(x.second);
     dev_free(b->d_items);

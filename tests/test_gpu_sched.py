@@ -269,3 +269,27 @@ def test_learned_split_roots_are_exact():
         _, rc_plain = api.count(g, tr, root_cost=True)
         _, rc_learn = api.count(g, tr, root_cost=True, model=m, sample=1)
         assert np.array_equal(rc_plain, rc_learn)
+
+
+def test_learned_batch_split_roots_are_exact():
+    """The batch schedule from the steep model: heavy segments of the burst
+    graph go first as single roots in parts, the rest in time order."""
+    rng = np.random.default_rng(13)
+    s1, d1, t1 = tiny_graph(rng, 40, 600, 30, self_loops=True)
+    s2, d2, t2 = tiny_graph(rng, 40, 6000, 200_000, self_loops=True)
+    burst = (np.concatenate([s1, s2]), np.concatenate([d1, d2]), np.concatenate([t1, t2 + 1000]))
+    plain = tiny_graph(rng, 30, 3000, 5000, self_loops=True)
+    graphs, trees, want = [], [], []
+    for j, ((s, d, t), n) in enumerate([(burst, 40), (plain, 30), (burst, 40)]):
+        ms = W.random_extension_motifs(12, (2, 3, 4), 5, 40 + j)
+        delta = (20, 50, 90)[j]
+        og = OracleGraph(s, d, t, n)
+        graphs.append(api.Graph(s, d, t, n))
+        trees.append(api.Tree(ms, delta))
+        want.append(np.array([og.count(x, delta) for x in ms], dtype=np.uint64))
+    say("learned batch, split roots")
+    b = api.Batch(graphs, trees, model=_steep_model())
+    assert b.info()["learned"] == 1
+    for _ in range(3):
+        for a, w in zip(b.count(), want):
+            assert np.array_equal(a, w)
