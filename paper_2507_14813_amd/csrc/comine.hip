@@ -271,7 +271,7 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
             if (x < nA) ng = inode[A.node[x]] >> 20;
             const uint32_t incl = incl_scan32(ng, lane) + P;
             if (x < nA) A.pincl[x] = (uint16_t)incl;
-            P = uniform(__shfl(incl, kWave - 1));
+            P = lane_value(incl, kWave - 1);
         }
         wave_sync();
     }
@@ -358,7 +358,10 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                     }
                 }
                 // take the longest prefix of pairs whose candidates stay below 2^31
-                const uint64_t incl64 = incl_scan64((uint64_t)len, lane);
+                // (32-bit sums are exact unless some window has 2^26 entries)
+                const uint64_t incl64 = __ballot(len >= (1u << 26))
+                                            ? incl_scan64((uint64_t)len, lane)
+                                            : (uint64_t)incl_scan32(len, lane);
                 const bool take = pi < P && incl64 <= kChunkLimit;
                 pc += uniform((uint32_t)__popcll(__ballot(take)));
                 const bool own = part == 0;   // this part keeps the per-window work
@@ -412,7 +415,7 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                 wrec.z = __shfl(incl - lk, from);
                 wrec.w = __shfl(incl, from);
                 if ((uint32_t)lane >= nw) wrec = make_uint4(0, 0, 0, 0);
-                T = nw ? uniform(__shfl(wrec.w, (int)nw - 1)) : 0u;
+                T = nw ? lane_value(wrec.w, nw - 1) : 0u;
                 cc = 0;
                 if (L == 1 && nparts > 1) {
                     // one root, so every window fits this one chunk
@@ -627,7 +630,7 @@ comine_kernel(const KParams<TT> p) {
         for (;;) {
             unsigned long long it = 0;
             if (lane == 0) it = atomicAdd(&p.queues[kQueues * kQueueStride], 1ull);
-            it = __shfl(it, 0);
+            it = lane0_u64(it);
             if (it >= n_items) break;
             const uint2 item = p.items[uniform((uint32_t)it)];
             const uint32_t iy = uniform(item.y);
@@ -653,7 +656,7 @@ comine_kernel(const KParams<TT> p) {
         for (;;) {
             unsigned long long got = 0;
             if (lane == 0) got = atomicAdd(&p.queues[q * kQueueStride], (unsigned long long)p.chunk);
-            got = __shfl(got, 0);
+            got = lane0_u64(got);
             if (got >= (unsigned long long)(qend - qbeg)) break;
             const uint32_t base = uniform(qbeg + (uint32_t)got);
             if (p.skip && p.skip[base / kWave]) continue;   // searched as an item
@@ -689,7 +692,7 @@ batch_kernel(const BatchParams<TT> bp) {
     for (;;) {
         unsigned long long it = 0;
         if (lane == 0) it = atomicAdd(bp.cursor, 1ull);
-        it = __shfl(it, 0);
+        it = lane0_u64(it);
         if (it >= bp.n_items) break;
         const BatchItem item = bp.items[uniform((uint32_t)it)];
         const BatchJob<TT> &job = bp.jobs[uniform(item.job)];

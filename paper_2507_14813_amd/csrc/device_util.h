@@ -23,13 +23,27 @@ static __device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-static __device__ __forceinline__ uint32_t incl_scan32(uint32_t v, int lane) {
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        uint32_t o = __shfl_up(v, d);
-        if (lane >= d) v += o;
-    }
-    return v;
+// Inclusive wave64 prefix sum by DPP: shifts by 1, 2, 4, 8 within each row of
+// 16 lanes (lanes shifted in from outside the row read 0), then the total of
+// row 0 is added to row 1 and of row 2 to row 3 (row_bcast:15, rows 1 and 3
+// written), then the total of rows 0-1 to rows 2 and 3 (row_bcast:31).
+static __device__ __forceinline__ uint32_t incl_scan32(uint32_t x, int /*lane*/) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true);   // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, true);   // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, true);   // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, true);   // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return x;
+}
+
+// value of v in lane `src`, which must be the same in every lane
+static __device__ __forceinline__ uint32_t lane_value(uint32_t v, uint32_t src) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)src);
+}
+static __device__ __forceinline__ unsigned long long lane0_u64(unsigned long long v) {
+    const uint32_t lo = lane_value((uint32_t)v, 0), hi = lane_value((uint32_t)(v >> 32), 0);
+    return ((unsigned long long)hi << 32) | lo;
 }
 
 static __device__ __forceinline__ uint64_t incl_scan64(uint64_t v, int lane) {
