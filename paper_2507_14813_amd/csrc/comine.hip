@@ -402,20 +402,24 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                 // candidate ranges are numbered without the leaf-counted ones
                 // (the chunk total stays below the limit checked above)
                 const bool keep = take && len > 0 && !leaf;
-                const uint32_t lk = keep ? len : 0u;
-                const uint32_t incl = incl_scan32(lk, lane);
                 const uint64_t km = __ballot(keep);
                 nw = uniform((uint32_t)__popcll(km));
-                if (keep) W.src[mbcnt(km)] = (uint8_t)lane;
-                wave_sync();
-                const int from = (uint32_t)lane < nw ? (int)W.src[lane] : lane;
-                wave_sync();
-                wrec.x = __shfl(x | (g << 8), from);
-                wrec.y = __shfl(l0, from);
-                wrec.z = __shfl(incl - lk, from);
-                wrec.w = __shfl(incl, from);
-                if ((uint32_t)lane >= nw) wrec = make_uint4(0, 0, 0, 0);
-                T = nw ? lane_value(wrec.w, nw - 1) : 0u;
+                wrec = make_uint4(0, 0, 0, 0);
+                T = 0;
+                if (nw) {
+                    const uint32_t lk = keep ? len : 0u;
+                    const uint32_t incl = incl_scan32(lk, lane);
+                    if (keep) W.src[mbcnt(km)] = (uint8_t)lane;
+                    wave_sync();
+                    const int from = (uint32_t)lane < nw ? (int)W.src[lane] : lane;
+                    wave_sync();
+                    wrec.x = __shfl(x | (g << 8), from);
+                    wrec.y = __shfl(l0, from);
+                    wrec.z = __shfl(incl - lk, from);
+                    wrec.w = __shfl(incl, from);
+                    if ((uint32_t)lane >= nw) wrec = make_uint4(0, 0, 0, 0);
+                    T = lane_value(wrec.w, nw - 1);
+                }
                 cc = 0;
                 if (L == 1 && nparts > 1) {
                     // one root, so every window fits this one chunk
