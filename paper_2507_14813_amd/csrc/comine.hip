@@ -63,24 +63,23 @@ __device__ __forceinline__ uint32_t credit_child(uint32_t word, uint32_t c,
     return c;
 }
 
-// Counts a leaf-only window [l0, l0 + len) of one adjacency list for the
-// partial match with bound vertices ph[0..nvp): each entry reaches the child
-// of the bound vertex it hits, or the new-vertex child.  The bound vertices
-// are distinct, so an entry hits at most one of them: one equality count per
-// bound vertex, and the new-vertex count is what is left.  Returns the credits.
-template <typename TT, int SA>
-__device__ __forceinline__ uint32_t leaf_scan_window(const Entry<TT> *__restrict__ adj,
-                                                     uint32_t l0, uint32_t len,
-                                                     const int32_t (&ph)[SA], uint32_t nvp,
-                                                     const uint4 ga, const uint4 gb,
-                                                     unsigned long long *cnt) {
-    int32_t q[SA];
-    uint32_t c[SA];
+// Counts a leaf-only window [l0, l0 + len) of one adjacency list for one
+// partial match: each entry reaches the child of the bound vertex it hits, or
+// the new-vertex child.  The bound vertices are distinct, so an entry hits at
+// most one of them: one equality count per bound vertex, and the new-vertex
+// child gets the rest of the window.  The list's own anchor is left out of
+// q[] (no entry equals it: lists hold no self-loops); q[0..K) are the other
+// bound vertices (-1 for none) and w[0..K) their child words, wn the
+// new-vertex child's word.  Returns the credits.
+template <typename TT, int K, int N>
+__device__ __forceinline__ uint32_t leaf_count(const Entry<TT> *__restrict__ adj, uint32_t l0,
+                                               uint32_t len, const int32_t (&q)[N],
+                                               const uint32_t (&w)[N], uint32_t wn,
+                                               unsigned long long *cnt) {
+    static_assert(K <= N, "slots");
+    uint32_t c[K];
 #pragma unroll
-    for (int s = 0; s < SA; ++s) {
-        q[s] = (uint32_t)s < nvp ? ph[s] : -1;   // graph vertex ids are >= 0
-        c[s] = 0;
-    }
+    for (int s = 0; s < K; ++s) c[s] = 0;
     const Entry<TT> *e = adj + l0;
     uint32_t i = 0;
     for (; i + 4 <= len; i += 4) {
@@ -90,21 +89,31 @@ __device__ __forceinline__ uint32_t leaf_scan_window(const Entry<TT> *__restrict
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int s = 0; s < SA; ++s) c[s] += v[j] == q[s];
+            for (int s = 0; s < K; ++s) c[s] += v[j] == q[s];
     }
     for (; i < len; ++i) {
         const int32_t v = e[i].v;
 #pragma unroll
-        for (int s = 0; s < SA; ++s) c[s] += v == q[s];
+        for (int s = 0; s < K; ++s) c[s] += v == q[s];
     }
-    const uint32_t words[6] = {ga.y, ga.z, ga.w, gb.x, gb.y, gb.z};
     uint32_t hit = 0, got = 0;
 #pragma unroll
-    for (int s = 0; s < SA; ++s) {
+    for (int s = 0; s < K; ++s) {
         hit += c[s];
-        got += credit_child(words[s], c[s], cnt);
+        got += credit_child(w[s], c[s], cnt);
     }
-    return got + credit_child(gb.w, len - hit, cnt);
+    return got + credit_child(wn, len - hit, cnt);
+}
+
+// child word of bound slot s (0..5) of a group record
+__device__ __forceinline__ uint32_t slot_word(const uint4 &a, const uint4 &b, uint32_t s) {
+    uint32_t r = b.z;
+    r = s == 0 ? a.y : r;
+    r = s == 1 ? a.z : r;
+    r = s == 2 ? a.w : r;
+    r = s == 3 ? b.x : r;
+    r = s == 4 ? b.y : r;
+    return r;
 }
 
 // Counts the leaf-only window [l0, l0 + len) of group g for buffered partial
@@ -381,13 +390,35 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                 const bool leaf = take && len > 0 && p.leaf_scan && ((hdr >> 12) & 1);
                 const bool scanned = leaf && len <= p.leaf_scan;
                 const bool coop = leaf && len > p.leaf_scan;
-                if (scanned && own) {
-                    int32_t ph[SA];
+                // bound vertices to compare with, the anchor left out; the
+                // count loop is compiled for the wave's largest number
+                const uint32_t nq = scanned && own ? ((hdr >> 8) & 15) - 1u : 0u;
+                uint32_t nqm = 0;
 #pragma unroll
-                    for (int s = 0; s < SA; ++s) ph[s] = A.phi[s][x];
-                    const uint32_t c = leaf_scan_window<TT, SA>(
-                        (hdr & 15) == kDirOut ? p.g.out_adj : p.g.in_adj, l0, len, ph,
-                        (hdr >> 8) & 15, grp[2 * g], grp[2 * g + 1], cnt);
+                for (int k = 1; k < SA; ++k) nqm += __ballot(nq >= (uint32_t)k) ? 1u : 0u;
+                if (scanned && own) {
+                    constexpr int NQ = SA - 1;
+                    const uint32_t anc = (hdr >> 4) & 15;
+                    const uint4 ga = grp[2 * g], gb = grp[2 * g + 1];
+                    int32_t q[NQ];
+                    uint32_t w[NQ];
+#pragma unroll
+                    for (int i = 0; i < NQ; ++i) {
+                        const uint32_t sl = (uint32_t)i + ((uint32_t)i >= anc ? 1u : 0u);
+                        const bool on = (uint32_t)i < nq;
+                        int32_t v = -1;
+#pragma unroll
+                        for (int t = 0; t < SA; ++t) v = (on && sl == (uint32_t)t) ? A.phi[t][x] : v;
+                        q[i] = v;
+                        w[i] = on ? slot_word(ga, gb, sl) : 0u;
+                    }
+                    const Entry<TT> *adj = (hdr & 15) == kDirOut ? p.g.out_adj : p.g.in_adj;
+                    uint32_t c = 0;
+                    if constexpr (NQ >= 1) if (nqm == 1) c = leaf_count<TT, 1>(adj, l0, len, q, w, gb.w, cnt);
+                    if constexpr (NQ >= 2) if (nqm == 2) c = leaf_count<TT, 2>(adj, l0, len, q, w, gb.w, cnt);
+                    if constexpr (NQ >= 3) if (nqm == 3) c = leaf_count<TT, 3>(adj, l0, len, q, w, gb.w, cnt);
+                    if constexpr (NQ >= 4) if (nqm == 4) c = leaf_count<TT, 4>(adj, l0, len, q, w, gb.w, cnt);
+                    if constexpr (NQ >= 5) if (nqm == 5) c = leaf_count<TT, 5>(adj, l0, len, q, w, gb.w, cnt);
                     if constexpr (STATS) st.v[kStatCredit] += c;
                 }
                 for (uint64_t cm = __ballot(coop && own); cm; cm &= cm - 1) {

@@ -166,6 +166,12 @@ def test_search_statistics_match_oracle():
     assert st["roots"] == int((s != d).sum())
     for k, v in want.items():
         assert st[k] == v, (k, st[k], v)
+    # every way of counting leaf windows (lane, whole wave, candidate expansion)
+    # gives the same statistics
+    for ls in (1, 4, -1):
+        say("stats, leaf_scan", ls)
+        c2, st2 = api.count(g, tr, stats=True, leaf_scan=ls)
+        assert np.array_equal(c2, counts) and st2 == st, ls
 
 
 def _root_cost_expectation(og, motifs, delta, n_edges, src, dst):
