@@ -178,7 +178,7 @@ def bench_learned(args):
     import numpy as np
     import torch
     from paper_2507_14813_amd import api, workloads as W
-    wl = W.make_config(4, scale=args.scale)
+    wl = W.make_config(4, scale=args.scale, progress=lambda m: log("generator:", m))
     s, d, t, n = wl.graphs[0]
     ms, delta = wl.motif_sets[0], wl.deltas[0]
     E = len(s)
@@ -236,7 +236,7 @@ def bench_sweep(args):
     import torch
     from paper_2507_14813_amd import api, workloads as W
     t0 = time.perf_counter()
-    wl = W.make_config(5, scale=args.scale)
+    wl = W.make_config(5, scale=args.scale, progress=lambda m: log("generator:", m))
     s, d, t, n = wl.graphs[0]
     ms = wl.motif_sets[0]
     E = len(s)
@@ -333,7 +333,7 @@ def main():
         torch.cuda.synchronize()
         del a, b
     t0 = time.perf_counter()
-    wl = W.make_config(2, scale=args.scale)
+    wl = W.make_config(2, scale=args.scale, progress=lambda m: log("generator:", m))
     s, d, t, n = wl.graphs[0]
     motifs, delta = wl.motif_sets[0], wl.deltas[0]
     E = len(s)

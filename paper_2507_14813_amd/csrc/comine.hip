@@ -116,14 +116,13 @@ __device__ __forceinline__ uint32_t slot_word(const uint4 &a, const uint4 &b, ui
     return r;
 }
 
-// Counts the leaf-only window [l0, l0 + len) of group g for buffered partial
-// match x with the whole wave, 64 entries per pass: one ballot per bound
+// Counts the leaf-only window [l0, l0 + len) of group g for the partial match
+// with bound vertices ph[] with the whole wave, 64 entries per pass: one ballot per bound
 // vertex counts the entries that hit it, and the new-vertex child gets the
 // rest.  All arguments are wave-uniform.  Returns the credits on lane 0
 // (0 on the other lanes).
-template <typename TT, int SA, int CAP>
-__device__ __forceinline__ uint32_t leaf_scan_wave(const KParams<TT> &p,
-                                                   const int32_t (&phi)[SA][CAP], uint32_t x,
+template <typename TT, int SA>
+__device__ __forceinline__ uint32_t leaf_scan_wave(const KParams<TT> &p, const int32_t (&ph)[SA],
                                                    uint32_t g, uint32_t l0, uint32_t len,
                                                    const int lane, unsigned long long *cnt) {
     const uint4 ga = p.tree.grp[2 * g], gb = p.tree.grp[2 * g + 1];
@@ -134,7 +133,7 @@ __device__ __forceinline__ uint32_t leaf_scan_wave(const KParams<TT> &p,
     uint32_t c[SA];
 #pragma unroll
     for (int s = 0; s < SA; ++s) {
-        q[s] = (uint32_t)s < nvp ? (int32_t)uniform((uint32_t)phi[s][x]) : -1;
+        q[s] = (uint32_t)s < nvp ? ph[s] : -1;
         c[s] = 0;
     }
     uint32_t i = 0;
@@ -171,8 +170,9 @@ template <typename TT, int L, bool R>
 struct LevelBuf {
     static constexpr int S = (2 * L < kVMax) ? 2 * L : kVMax;   // vertex slots
     static constexpr int C = 2 * kWave;                          // capacity
-    int32_t phi[S][C];     // phi[s][i]: graph vertex of motif vertex s
-    TT tfirst[C];
+    // phi[s - 2][i]: graph vertex of motif vertex s >= 2; motif vertices 0 and
+    // 1 and t_first are the root's, kept once in the level-1 batch (slot r1)
+    int32_t phi[S - 2][C];
     TT tprev[C];
     uint16_t node[C];      // internal trie node reached
     uint16_t pincl[C];     // inclusive prefix of child-group counts
@@ -202,8 +202,8 @@ struct LevelChain<TT, D, R, D> {};
 // 64-bit atomics require.
 //
 // Root windows: for each root of the level-1 batch, the windows it found in
-// out(a), in(a), out(b), in(b) (index anchor * 2 + direction; lo > hi when not
-// found yet).  A deeper partial match of that root reads a window of the same
+// out(a), in(a), out(b), in(b) (index anchor * 2 + direction): first entry and
+// length, kNoHint as length when not found yet or 65535 entries or longer.  A deeper partial match of that root reads a window of the same
 // list with t_prev < t <= t_first + delta, t_prev > t_first: it starts inside
 // the root's window and ends where it ends, so a bisection over the root's
 // window replaces a bisection over the whole list and the search for the end.
@@ -213,7 +213,7 @@ struct alignas(16) WaveLds {
     uint8_t src[kWave];           // window compaction: lane holding the k-th window
     uint8_t flag[kWave];          // window-end marks of one pass
     uint32_t hlo[H][kWave];       // root windows (used when D > 2)
-    uint32_t hhi[H][kWave];
+    uint16_t hlen[H][kWave];
     LevelChain<TT, D, R, 1> lv;
 };
 
@@ -222,19 +222,17 @@ static_assert(sizeof(WaveLds<uint32_t, 3, false>) % 16 == 0, "per-wave LDS block
 static_assert(sizeof(WaveLds<uint32_t, 5, false>) % 16 == 0, "per-wave LDS block size");
 static_assert(sizeof(WaveLds<uint64_t, 5, true>) % 16 == 0, "per-wave LDS block size");
 
-// A new root in level-1 slot `slot`: its root windows are not found yet
-// (lo > hi), and the lo words of out(a) and in(b) hold where the search for
-// those windows starts, just after the root edge's own index (pos + 1 >= 1).
+constexpr uint16_t kNoHint = 0xffff;
+
+// A new root in level-1 slot `slot`: its root windows are not found yet, and
+// the first-entry words of out(a) and in(b) hold where the search for those
+// windows starts, just after the root edge's own index.
 template <typename TT, int D, bool R>
 __device__ __forceinline__ void set_root_slot(WaveLds<TT, D, R> &W, uint32_t slot, uint2 pos) {
     W.hlo[0][slot] = pos.x + 1u;
-    W.hhi[0][slot] = 0u;
-    W.hlo[1][slot] = 1u;
-    W.hhi[1][slot] = 0u;
-    W.hlo[2][slot] = 1u;
-    W.hhi[2][slot] = 0u;
     W.hlo[3][slot] = pos.y + 1u;
-    W.hhi[3][slot] = 0u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) W.hlen[k][slot] = kNoHint;
 }
 
 template <int L, typename TT, int D, bool R, int M>
@@ -262,6 +260,16 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
     constexpr bool STATS = MODE == 1, LOG = MODE == 2;
     LevelBuf<TT, L, LOG> &A = lvl<L>(W.lv);
     constexpr int SA = LevelBuf<TT, L, LOG>::S;
+    LevelBuf<TT, 1, LOG> &R1 = lvl<1>(W.lv);
+    // graph vertex of motif vertex s, and t_first, of buffered partial match i
+    auto vtx = [&](uint32_t s, uint32_t i) -> int32_t {
+        if constexpr (L == 1) return A.phi[s][i];
+        else return s < 2 ? R1.phi[s][A.r1[i]] : A.phi[s < 2 ? 0 : s - 2][i];
+    };
+    auto tfirst_of = [&](uint32_t i) -> TT {
+        if constexpr (L == 1) return A.tfirst[i];
+        else return R1.tfirst[A.r1[i]];
+    };
     const uint32_t *__restrict__ inode = p.tree.inode;
     const uint4 *__restrict__ grp = p.tree.grp;
     const uint64_t le_mask = (lane == 63) ? ~0ull : ((2ull << lane) - 1);
@@ -322,7 +330,7 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                     x = lo;
                     hdr = grp[2 * g].x;
                     const int dir = hdr & 15, anc = (hdr >> 4) & 15;
-                    const TT thi = sat_add(A.tfirst[lo], p.delta_sat);
+                    const TT thi = sat_add(tfirst_of(lo), p.delta_sat);
                     uint32_t b, e, sh;
                     const TT *ta;
                     bool hinted = false;
@@ -336,13 +344,14 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                             if (anc < 2) {
                                 const uint32_t k = (uint32_t)anc * 2u + (uint32_t)dir;
                                 const uint32_t r1 = A.r1[lo];
+                                const uint32_t hl = W.hlen[k][r1];
+                                hinted = hl != kNoHint;
                                 b = W.hlo[k][r1];
-                                e = W.hhi[k][r1];
-                                hinted = b <= e;
+                                e = b + hl;
                             }
                         }
                         if (!hinted) {
-                            const int32_t a = A.phi[anc][lo];
+                            const int32_t a = vtx((uint32_t)anc, lo);
                             const uint32_t *off = dir == kDirOut ? p.g.out_off : p.g.in_off;
                             b = off[a]; e = off[a + 1];
                         }
@@ -362,7 +371,7 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                         if (!all && anc < 2) {
                             const uint32_t k = (uint32_t)anc * 2u + (uint32_t)dir;
                             W.hlo[k][lo] = l0;
-                            W.hhi[k][lo] = l0 + len;
+                            W.hlen[k][lo] = len < kNoHint ? (uint16_t)len : kNoHint;
                         }
                     }
                 }
@@ -408,7 +417,7 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                         const bool on = (uint32_t)i < nq;
                         int32_t v = -1;
 #pragma unroll
-                        for (int t = 0; t < SA; ++t) v = (on && sl == (uint32_t)t) ? A.phi[t][x] : v;
+                        for (int t = 0; t < SA; ++t) v = (on && sl == (uint32_t)t) ? vtx(t, x) : v;
                         q[i] = v;
                         w[i] = on ? slot_word(ga, gb, sl) : 0u;
                     }
@@ -423,9 +432,12 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                 }
                 for (uint64_t cm = __ballot(coop && own); cm; cm &= cm - 1) {
                     const int src = (int)__builtin_ctzll(cm);
+                    const uint32_t wx = __builtin_amdgcn_readlane(x, src);
+                    int32_t wph[SA];
+#pragma unroll
+                    for (int t = 0; t < SA; ++t) wph[t] = (int32_t)uniform((uint32_t)vtx(t, wx));
                     const uint32_t c = leaf_scan_wave<TT, SA>(
-                        p, A.phi, __builtin_amdgcn_readlane(x, src),
-                        __builtin_amdgcn_readlane(g, src), __builtin_amdgcn_readlane(l0, src),
+                        p, wph, __builtin_amdgcn_readlane(g, src), __builtin_amdgcn_readlane(l0, src),
                         __builtin_amdgcn_readlane(len, src), lane, cnt);
                     if constexpr (STATS) st.v[kStatCredit] += c;
                 }
@@ -479,6 +491,7 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
             const uint32_t ei = olo + (f - oex);
 
             uint32_t cw = 0;      // child word reached by this candidate
+            TT tn = 0;            // its time
             int dir = 0;
             uint32_t nvp = 0;
             int32_t nv0 = -1, nv1 = -1;
@@ -492,10 +505,12 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                 dir = ga.x & 15;
                 nvp = (ga.x >> 8) & 15;
 #pragma unroll
-                for (int s = 0; s < SA; ++s) ph[s] = A.phi[s][ox];
+                for (int s = 0; s < SA; ++s) ph[s] = vtx(s, ox);
                 if (dir != kDirAll) {
                     const Entry<TT> *adj = dir == kDirOut ? p.g.out_adj : p.g.in_adj;
-                    const int32_t v = adj[ei].v;
+                    const Entry<TT> en = adj[ei];   // one load: vertex and time
+                    const int32_t v = en.v;
+                    tn = en.t;
                     int y = -1;
 #pragma unroll
                     for (int s = 0; s < SA; ++s) y = ((uint32_t)s < nvp && ph[s] == v) ? s : y;
@@ -527,17 +542,15 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                 const bool push = (cw >> 31) != 0;
                 const uint64_t pm = __ballot(push);
                 if (push) {
-                    const TT tnew = dir == kDirAll ? p.g.gt[ei]
-                                    : (dir == kDirOut ? p.g.out_adj : p.g.in_adj)[ei].t;
+                    const TT tnew = dir == kDirAll ? p.g.gt[ei] : tn;
                     const uint32_t slot = nB + mbcnt(pm);
 #pragma unroll
-                    for (int s = 0; s < SB; ++s) {
+                    for (int s = 2; s < SB; ++s) {
                         int32_t v = (s < SA) ? ph[s < SA ? s : 0] : -1;
                         v = ((uint32_t)s < nvp) ? v
                             : ((uint32_t)s == nvp ? nv0 : ((uint32_t)s == nvp + 1 ? nv1 : -1));
-                        B.phi[s][slot] = v;
+                        B.phi[s - 2][slot] = v;
                     }
-                    B.tfirst[slot] = A.tfirst[ox];
                     B.tprev[slot] = tnew;
                     B.node[slot] = (uint16_t)(cw & 0xffffu);
                     if constexpr (L == 1) B.r1[slot] = (uint8_t)ox;

@@ -85,7 +85,7 @@ def _draw_from_weights(rng, w, n):
 def powerlaw_graph(n_nodes: int, n_edges: int, gamma: float, span: int,
                    seed: int, gamma_in: float | None = None,
                    burst_alpha: float = 1.5, gap_mean: float = 30.0,
-                   reuse_p: float = 0.5, burst_cap: int | None = None):
+                   reuse_p: float = 0.5, burst_cap: int | None = None, progress=None):
     """Heavy-tailed bursty directed temporal graph (seeded).
 
     Recipe (a reading: the paper gives only the dataset statistics):
@@ -105,8 +105,10 @@ def powerlaw_graph(n_nodes: int, n_edges: int, gamma: float, span: int,
        previous edge's destination with probability ``reuse_p``.
     5. All edges are stably sorted by t.
 
-    Returns (src int32, dst int32, t int64).
+    Returns (src int32, dst int32, t int64).  ``progress``, when given, is
+    called with the name of each finished stage (large graphs take minutes).
     """
+    say = progress or (lambda _msg: None)
     rng = _rng(seed)
     gamma_in = gamma if gamma_in is None else gamma_in
     cap = math.sqrt(n_edges)
@@ -117,6 +119,7 @@ def powerlaw_graph(n_nodes: int, n_edges: int, gamma: float, span: int,
     deg = rng.multinomial(n_edges, w_out / w_out.sum()).astype(np.int64)
     src = np.repeat(np.arange(n_nodes, dtype=np.int64), deg)
     E = n_edges
+    say("degrees")
 
     # burst boundaries: a global Pareto size stream plus every source start
     sizes = []
@@ -139,6 +142,7 @@ def powerlaw_graph(n_nodes: int, n_edges: int, gamma: float, span: int,
     start_flag[node_start] = True
     burst_id = np.cumsum(start_flag) - 1
     n_bursts = int(burst_id[-1]) + 1 if E else 0
+    say("bursts")
 
     # timestamps
     bstart = rng.integers(0, span, n_bursts, dtype=np.int64).astype(np.float64)
@@ -149,6 +153,7 @@ def powerlaw_graph(n_nodes: int, n_edges: int, gamma: float, span: int,
     offset = c - c[first_idx][burst_id]
     t = np.floor(bstart[burst_id] + offset).astype(np.int64)
     np.clip(t, 0, span - 1, out=t)
+    say("timestamps")
 
     # destinations
     fresh = _draw_from_weights(rng, w_in, E)
@@ -161,8 +166,10 @@ def powerlaw_graph(n_nodes: int, n_edges: int, gamma: float, span: int,
     idx = np.where(reuse, 0, np.arange(E, dtype=np.int64))
     np.maximum.accumulate(idx, out=idx)
     dst = fresh[idx]
+    say("destinations")
 
     order = np.argsort(t, kind="stable")
+    say("time order")
     return (src[order].astype(np.int32), dst[order].astype(np.int32),
             t[order].astype(np.int64))
 
@@ -241,8 +248,9 @@ class Workload:
     note: str = ""
 
 
-def make_config(k: int, scale: float = 1.0) -> Workload:
-    """The five synthetic workloads; ``scale`` shrinks edge and node counts."""
+def make_config(k: int, scale: float = 1.0, progress=None) -> Workload:
+    """The five synthetic workloads; ``scale`` shrinks edge and node counts;
+    ``progress`` is passed to the graph generator."""
     def sc(x):
         return max(16, int(round(x * scale)))
 
@@ -253,7 +261,7 @@ def make_config(k: int, scale: float = 1.0) -> Workload:
                         [(*g, V)], [list(CONFIG1_MOTIFS)], [10_000])
     if k == 2:
         V, E = sc(1_000_000), sc(20_000_000)
-        g = powerlaw_graph(V, E, 2.1, 30_000_000, seed=2)
+        g = powerlaw_graph(V, E, 2.1, 30_000_000, seed=2, progress=progress)
         return Workload(
             "powerlaw V=%d E=%d gamma=2.1 span=3e7 delta=3600, 36 motifs" % (V, E),
             [(*g, V)], [enumerate_motifs(3, 3)], [3600])
@@ -280,7 +288,7 @@ def make_config(k: int, scale: float = 1.0) -> Workload:
         # burst sizes capped at 64 (calibration: uncapped Pareto bursts make a
         # few roots explode combinatorially for 4-edge motifs; with the cap the
         # top 1% of roots still hold most of the work)
-        g = powerlaw_graph(V, E, 1.8, 30_000_000, seed=4, burst_cap=64)
+        g = powerlaw_graph(V, E, 1.8, 30_000_000, seed=4, burst_cap=64, progress=progress)
         ms = enumerate_motifs(3, 4) + enumerate_motifs(4, 4)
         return Workload(
             "powerlaw V=%d E=%d gamma=1.8 delta=7200, 756 motifs" % (V, E),
@@ -288,7 +296,7 @@ def make_config(k: int, scale: float = 1.0) -> Workload:
     if k == 5:
         V, E = sc(20_000_000), sc(200_000_000)
         # burst sizes capped at 32 (5-edge motifs, windows up to 6 hours)
-        g = powerlaw_graph(V, E, 2.0, 100_000_000, seed=5, burst_cap=32)
+        g = powerlaw_graph(V, E, 2.0, 100_000_000, seed=5, burst_cap=32, progress=progress)
         ms = (random_extension_motifs(16, (3,), 5, 51)
               + random_extension_motifs(16, (4,), 5, 52)
               + random_extension_motifs(16, (5,), 5, 53))
