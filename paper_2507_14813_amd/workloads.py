@@ -73,12 +73,18 @@ def _pareto_weights(rng, n, gamma, cap):
     return np.minimum(w, cap)
 
 
-def _draw_from_weights(rng, w, n):
-    """n i.i.d. draws of indices with probability proportional to w."""
+def _draw_from_weights(rng, w, n, progress=None):
+    """n i.i.d. draws of indices with probability proportional to w (the
+    lookup runs in pieces, reporting each to ``progress``)."""
     cdf = np.cumsum(w)
     cdf /= cdf[-1]
     x = rng.random(n)
-    idx = np.searchsorted(cdf, x, side="right")
+    idx = np.empty(n, dtype=np.int64)
+    step = 1 << 24
+    for a in range(0, n, step):
+        idx[a:a + step] = np.searchsorted(cdf, x[a:a + step], side="right")
+        if progress and n > step:
+            progress("weighted draws %d/%d" % (min(n, a + step), n))
     return np.minimum(idx, len(w) - 1)
 
 
@@ -156,7 +162,7 @@ def powerlaw_graph(n_nodes: int, n_edges: int, gamma: float, span: int,
     say("timestamps")
 
     # destinations
-    fresh = _draw_from_weights(rng, w_in, E)
+    fresh = _draw_from_weights(rng, w_in, E, say)
     bad = fresh == src
     while bad.any():
         fresh[bad] = _draw_from_weights(rng, w_in, int(bad.sum()))
