@@ -654,8 +654,15 @@ __device__ __forceinline__ void process_roots(const KParams<TT> &p,
     }
 }
 
+// Up to depth 3 the search fits 8 waves per SIMD (at most 64 VGPRs and 96
+// SGPRs) without spilling in its timed form; the compiler is asked for that.
+// Deeper trees keep the compiler's own allocation.
+template <int D>
+constexpr int min_waves_per_eu() { return D <= 3 ? 8 : 1; }
+
 template <typename TT, int D, int MODE>
 __global__ void __launch_bounds__(kWave * kWavesPerBlock)
+__attribute__((amdgpu_waves_per_eu(min_waves_per_eu<D>(), 8)))
 comine_kernel(const KParams<TT> p) {
     constexpr bool STATS = MODE == 1, LOG = MODE == 2;
     extern __shared__ __align__(16) unsigned char smem[];
