@@ -19,6 +19,7 @@ enum : int { kDirOut = 0, kDirIn = 1, kDirAll = 2 };
 
 // Search tables, as uploaded to the device.
 //   inode[i]  internal (non-leaf) trie node i: first group | group count << 20
+//             | count of the leading groups on a list of motif vertex 0 or 1 << 26
 //   grp[2g], grp[2g+1]: eight words of group g:
 //     w0 = dir | anchor << 4 | nv << 8 | leaf_only << 12
 //          (nv: vertices bound at the owning node; leaf_only: a per-vertex

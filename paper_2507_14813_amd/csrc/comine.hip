@@ -175,7 +175,8 @@ struct LevelBuf {
     int32_t phi[S - 2][C];
     TT tprev[C];
     uint16_t node[C];      // internal trie node reached
-    uint16_t pincl[C];     // inclusive prefix of child-group counts
+    uint16_t pincl[C];     // inclusive prefix of child-group counts: groups on
+    uint16_t pincl1[C];    // lists of motif vertex 0 or 1, then the others
     uint8_t r1[C];         // slot of its root in the level-1 batch
     uint32_t root[R ? C : 1];
 };
@@ -276,19 +277,31 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
 
 
     // child groups per buffered partial match -> inclusive prefix (at the
-    // root level every entry has the root's groups)
-    uint32_t P = 0;
-    const uint32_t root_ng = inode[0] >> 20;
+    // root level every entry has the root's groups).  Below it the pairs are
+    // taken in two classes: groups on a list of motif vertex 0 or 1 (windows
+    // found inside the root's windows: short bisections) first, then the
+    // others, so that the lanes of one pass do bisections of similar length.
+    uint32_t P = 0, P1 = 0, cls = 0;
+    const uint32_t root_ng = (inode[0] >> 20) & 63u;
     if constexpr (L == 1) {
         P = nA * root_ng;
     } else {
         for (uint32_t x0 = 0; x0 < nA; x0 += kWave) {
             const uint32_t x = x0 + lane;
-            uint32_t ng = 0;
-            if (x < nA) ng = inode[A.node[x]] >> 20;
-            const uint32_t incl = incl_scan32(ng, lane) + P;
-            if (x < nA) A.pincl[x] = (uint16_t)incl;
-            P = lane_value(incl, kWave - 1);
+            uint32_t n0 = 0, n1 = 0;
+            if (x < nA) {
+                const uint32_t w = inode[A.node[x]];
+                n0 = w >> 26;
+                n1 = ((w >> 20) & 63u) - n0;
+            }
+            const uint32_t i0 = incl_scan32(n0, lane) + P;
+            const uint32_t i1 = incl_scan32(n1, lane) + P1;
+            if (x < nA) {
+                A.pincl[x] = (uint16_t)i0;
+                A.pincl1[x] = (uint16_t)i1;
+            }
+            P = lane_value(i0, kWave - 1);
+            P1 = lane_value(i1, kWave - 1);
         }
         wave_sync();
     }
@@ -302,6 +315,13 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
     for (;;) {
         bool done = false;
         if (cc >= T) {
+            if constexpr (L > 1) {
+                if (pc >= P && cls == 0) {   // on to the second class of pairs
+                    cls = 1;
+                    P = P1;
+                    pc = 0;
+                }
+            }
             if (pc >= P) {
                 done = true;
             } else {
@@ -317,14 +337,16 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                         g = (inode[0] & 0xfffffu) + (pi - lo * root_ng);
                         tp = A.tfirst[lo];
                     } else {
+                        const uint16_t *pin = cls ? A.pincl1 : A.pincl;
                         uint32_t n = nA;
                         while (n > 0) {
                             const uint32_t h = n >> 1;
-                            if (A.pincl[lo + h] <= pi) { lo += h + 1; n -= h + 1; }
+                            if (pin[lo + h] <= pi) { lo += h + 1; n -= h + 1; }
                             else n = h;
                         }
-                        const uint32_t before = lo ? A.pincl[lo - 1] : 0u;
-                        g = (inode[A.node[lo]] & 0xfffffu) + (pi - before);
+                        const uint32_t before = lo ? pin[lo - 1] : 0u;
+                        const uint32_t w = inode[A.node[lo]];
+                        g = (w & 0xfffffu) + (cls ? (w >> 26) : 0u) + (pi - before);
                         tp = A.tprev[lo];
                     }
                     x = lo;

@@ -288,7 +288,18 @@ int build_tree(mg_tree *tr) {
         const int g0 = (int)tr->grp_tab.size() / 8;
         if (g0 + (int)groups.size() > (1 << 20))
             return fail(MG_EUNSUPPORTED, "too many child groups");
-        for (auto &kv : groups) {
+        // groups on a list of motif vertex 0 or 1 first: below the first
+        // level the search finds their windows inside the root's windows
+        std::vector<std::pair<std::pair<int, int>, std::vector<int>>> ordered;
+        for (int cls = 0; cls < 2; ++cls)
+            for (auto &kv : groups) {
+                const bool near = kv.first.first != mg::kDirAll && kv.first.second < 2;
+                if (near == (cls == 0)) ordered.push_back(kv);
+            }
+        int n_near = 0;
+        for (auto &kv : ordered)
+            n_near += (kv.first.first != mg::kDirAll && kv.first.second < 2) ? 1 : 0;
+        for (auto &kv : ordered) {
             bool leaf_only = kv.first.first != mg::kDirAll;
             for (int c : kv.second) leaf_only = leaf_only && tr->nodes[c].kids.empty();
             int32_t rec[8] = {kv.first.first | (kv.first.second << 4) | (nd.nv << 8) |
@@ -304,7 +315,8 @@ int build_tree(mg_tree *tr) {
             }
             tr->grp_tab.insert(tr->grp_tab.end(), rec, rec + 8);
         }
-        tr->node_tab[iidx[n]] = (int32_t)((uint32_t)g0 | ((uint32_t)groups.size() << 20));
+        tr->node_tab[iidx[n]] = (int32_t)((uint32_t)g0 | ((uint32_t)groups.size() << 20) |
+                                          ((uint32_t)n_near << 26));
     }
     if (tr->grp_tab.empty()) tr->grp_tab.assign(8, 0);
     tr->root_q = tr->nodes[0].q;
