@@ -306,9 +306,9 @@ def main():
                     help="also run a 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the search shards by root time range with one "
-              "count all-reduce, but multi-GPU runs are not part of this build",
-              file=sys.stderr)
+        print("bench.py runs on one GPU only (--gpus 1); a multi-GPU run would shard the "
+              "roots by time range and sum the counts with one all-reduce, which is not "
+              "implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
