@@ -71,6 +71,8 @@ __device__ __forceinline__ uint32_t credit_child(uint32_t word, uint32_t c,
 // q[] (no entry equals it: lists hold no self-loops); q[0..K) are the other
 // bound vertices (-1 for none) and w[0..K) their child words, wn the
 // new-vertex child's word.  Returns the credits.
+constexpr int kLeafUnroll = 8;
+
 template <typename TT, int K, int N>
 __device__ __forceinline__ uint32_t leaf_count(const Entry<TT> *__restrict__ adj, uint32_t l0,
                                                uint32_t len, const int32_t (&q)[N],
@@ -80,21 +82,20 @@ __device__ __forceinline__ uint32_t leaf_count(const Entry<TT> *__restrict__ adj
     uint32_t c[K];
 #pragma unroll
     for (int s = 0; s < K; ++s) c[s] = 0;
+    // kLeafUnroll independent loads per step, the last step included: an
+    // index past the window reloads its last entry (len >= 1) and counts as
+    // no hit, so a window of up to kLeafUnroll entries costs one memory trip
     const Entry<TT> *e = adj + l0;
-    uint32_t i = 0;
-    for (; i + 4 <= len; i += 4) {
-        int32_t v[4];
+    for (uint32_t i = 0; i < len; i += kLeafUnroll) {
+        int32_t v[kLeafUnroll];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) v[j] = e[i + j].v;
+        for (int j = 0; j < kLeafUnroll; ++j) v[j] = e[min(i + j, len - 1)].v;
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < kLeafUnroll; ++j) {
+            const bool in = i + j < len;
 #pragma unroll
-            for (int s = 0; s < K; ++s) c[s] += v[j] == q[s];
-    }
-    for (; i < len; ++i) {
-        const int32_t v = e[i].v;
-#pragma unroll
-        for (int s = 0; s < K; ++s) c[s] += v == q[s];
+            for (int s = 0; s < K; ++s) c[s] += (in && v[j] == q[s]) ? 1u : 0u;
+        }
     }
     uint32_t hit = 0, got = 0;
 #pragma unroll
