@@ -71,9 +71,7 @@ __device__ __forceinline__ uint32_t credit_child(uint32_t word, uint32_t c,
 // q[] (no entry equals it: lists hold no self-loops); q[0..K) are the other
 // bound vertices (-1 for none) and w[0..K) their child words, wn the
 // new-vertex child's word.  Returns the credits.
-constexpr int kLeafUnroll = 8;
-
-template <typename TT, int K, int N>
+template <int U, int K, typename TT, int N>
 __device__ __forceinline__ uint32_t leaf_count(const Entry<TT> *__restrict__ adj, uint32_t l0,
                                                uint32_t len, const int32_t (&q)[N],
                                                const uint32_t (&w)[N], uint32_t wn,
@@ -82,16 +80,16 @@ __device__ __forceinline__ uint32_t leaf_count(const Entry<TT> *__restrict__ adj
     uint32_t c[K];
 #pragma unroll
     for (int s = 0; s < K; ++s) c[s] = 0;
-    // kLeafUnroll independent loads per step, the last step included: an
-    // index past the window reloads its last entry (len >= 1) and counts as
-    // no hit, so a window of up to kLeafUnroll entries costs one memory trip
+    // U independent loads per step, the last step included: an index past
+    // the window reloads its last entry (len >= 1) and counts as no hit, so a
+    // window of up to U entries costs one memory trip
     const Entry<TT> *e = adj + l0;
-    for (uint32_t i = 0; i < len; i += kLeafUnroll) {
-        int32_t v[kLeafUnroll];
+    for (uint32_t i = 0; i < len; i += U) {
+        int32_t v[U];
 #pragma unroll
-        for (int j = 0; j < kLeafUnroll; ++j) v[j] = e[min(i + j, len - 1)].v;
+        for (int j = 0; j < U; ++j) v[j] = e[min(i + j, len - 1)].v;
 #pragma unroll
-        for (int j = 0; j < kLeafUnroll; ++j) {
+        for (int j = 0; j < U; ++j) {
             const bool in = i + j < len;
 #pragma unroll
             for (int s = 0; s < K; ++s) c[s] += (in && v[j] == q[s]) ? 1u : 0u;
@@ -445,12 +443,14 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                         w[i] = on ? slot_word(ga, gb, sl) : 0u;
                     }
                     const Entry<TT> *adj = (hdr & 15) == kDirOut ? p.g.out_adj : p.g.in_adj;
+                    // loads per step (measured: 8 for trees up to depth 3, 4 deeper)
+                    constexpr int kLU = D <= 3 ? 8 : 4;
                     uint32_t c = 0;
-                    if constexpr (NQ >= 1) if (nqm == 1) c = leaf_count<TT, 1>(adj, l0, len, q, w, gb.w, cnt);
-                    if constexpr (NQ >= 2) if (nqm == 2) c = leaf_count<TT, 2>(adj, l0, len, q, w, gb.w, cnt);
-                    if constexpr (NQ >= 3) if (nqm == 3) c = leaf_count<TT, 3>(adj, l0, len, q, w, gb.w, cnt);
-                    if constexpr (NQ >= 4) if (nqm == 4) c = leaf_count<TT, 4>(adj, l0, len, q, w, gb.w, cnt);
-                    if constexpr (NQ >= 5) if (nqm == 5) c = leaf_count<TT, 5>(adj, l0, len, q, w, gb.w, cnt);
+                    if constexpr (NQ >= 1) if (nqm == 1) c = leaf_count<kLU, 1>(adj, l0, len, q, w, gb.w, cnt);
+                    if constexpr (NQ >= 2) if (nqm == 2) c = leaf_count<kLU, 2>(adj, l0, len, q, w, gb.w, cnt);
+                    if constexpr (NQ >= 3) if (nqm == 3) c = leaf_count<kLU, 3>(adj, l0, len, q, w, gb.w, cnt);
+                    if constexpr (NQ >= 4) if (nqm == 4) c = leaf_count<kLU, 4>(adj, l0, len, q, w, gb.w, cnt);
+                    if constexpr (NQ >= 5) if (nqm == 5) c = leaf_count<kLU, 5>(adj, l0, len, q, w, gb.w, cnt);
                     if constexpr (STATS) st.v[kStatCredit] += c;
                 }
                 for (uint64_t cm = __ballot(coop && own); cm; cm &= cm - 1) {
