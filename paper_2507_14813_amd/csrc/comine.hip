@@ -80,19 +80,29 @@ __device__ __forceinline__ uint32_t leaf_count(const Entry<TT> *__restrict__ adj
     uint32_t c[K];
 #pragma unroll
     for (int s = 0; s < K; ++s) c[s] = 0;
-    // U independent loads per step, the last step included: an index past
-    // the window reloads its last entry (len >= 1) and counts as no hit, so a
-    // window of up to U entries costs one memory trip
+    // U independent loads per step, the last step included: there an index
+    // past the window reloads its last entry (len >= 1) and counts as no hit,
+    // so a window of up to U entries costs one memory trip
     const Entry<TT> *e = adj + l0;
-    for (uint32_t i = 0; i < len; i += U) {
+    uint32_t i = 0;
+    for (; i + U <= len; i += U) {
+        int32_t v[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) v[j] = e[i + j].v;
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+#pragma unroll
+            for (int s = 0; s < K; ++s) c[s] += v[j] == q[s];
+    }
+    if (i < len) {
         int32_t v[U];
 #pragma unroll
         for (int j = 0; j < U; ++j) v[j] = e[min(i + j, len - 1)].v;
 #pragma unroll
         for (int j = 0; j < U; ++j) {
-            const bool in = i + j < len;
+            const int32_t x = i + j < len ? v[j] : -2;   // -2 matches no vertex
 #pragma unroll
-            for (int s = 0; s < K; ++s) c[s] += (in && v[j] == q[s]) ? 1u : 0u;
+            for (int s = 0; s < K; ++s) c[s] += x == q[s];
         }
     }
     uint32_t hit = 0, got = 0;
@@ -104,16 +114,6 @@ __device__ __forceinline__ uint32_t leaf_count(const Entry<TT> *__restrict__ adj
     return got + credit_child(wn, len - hit, cnt);
 }
 
-// child word of bound slot s (0..5) of a group record
-__device__ __forceinline__ uint32_t slot_word(const uint4 &a, const uint4 &b, uint32_t s) {
-    uint32_t r = b.z;
-    r = s == 0 ? a.y : r;
-    r = s == 1 ? a.z : r;
-    r = s == 2 ? a.w : r;
-    r = s == 3 ? b.x : r;
-    r = s == 4 ? b.y : r;
-    return r;
-}
 
 // Counts the leaf-only window [l0, l0 + len) of group g for the partial match
 // with bound vertices ph[] with the whole wave, 64 entries per pass: one ballot per bound
@@ -430,17 +430,18 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                     constexpr int NQ = SA - 1;
                     const uint32_t anc = (hdr >> 4) & 15;
                     const uint4 ga = grp[2 * g], gb = grp[2 * g + 1];
+                    int32_t ph[SA];
+#pragma unroll
+                    for (int t = 0; t < SA; ++t) ph[t] = vtx(t, x);
+                    const uint32_t words[6] = {ga.y, ga.z, ga.w, gb.x, gb.y, gb.z};
                     int32_t q[NQ];
                     uint32_t w[NQ];
 #pragma unroll
                     for (int i = 0; i < NQ; ++i) {
-                        const uint32_t sl = (uint32_t)i + ((uint32_t)i >= anc ? 1u : 0u);
-                        const bool on = (uint32_t)i < nq;
-                        int32_t v = -1;
-#pragma unroll
-                        for (int t = 0; t < SA; ++t) v = (on && sl == (uint32_t)t) ? vtx(t, x) : v;
-                        q[i] = v;
-                        w[i] = on ? slot_word(ga, gb, sl) : 0u;
+                        // slot i below the anchor, slot i + 1 from it on
+                        const bool below = (uint32_t)i < anc, on = (uint32_t)i < nq;
+                        q[i] = on ? (below ? ph[i] : ph[i + 1]) : -1;
+                        w[i] = on ? (below ? words[i] : words[i + 1]) : 0u;
                     }
                     const Entry<TT> *adj = (hdr & 15) == kDirOut ? p.g.out_adj : p.g.in_adj;
                     // loads per step (measured: 8 for trees up to depth 3, 4 deeper)
