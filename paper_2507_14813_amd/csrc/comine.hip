@@ -397,11 +397,15 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                     }
                 }
                 // take the longest prefix of pairs whose candidates stay below 2^31
-                // (32-bit sums are exact unless some window has 2^26 entries)
-                const uint64_t incl64 = __ballot(len >= (1u << 26))
-                                            ? incl_scan64((uint64_t)len, lane)
-                                            : (uint64_t)incl_scan32(len, lane);
-                const bool take = pi < P && incl64 <= kChunkLimit;
+                // (always all of them when every window is under 2^25 entries;
+                // 32-bit sums are exact unless some window has 2^26 entries)
+                bool take = pi < P;
+                if (__ballot(len >= (1u << 25))) {
+                    const uint64_t incl64 = __ballot(len >= (1u << 26))
+                                                ? incl_scan64((uint64_t)len, lane)
+                                                : (uint64_t)incl_scan32(len, lane);
+                    take = take && incl64 <= kChunkLimit;
+                }
                 pc += uniform((uint32_t)__popcll(__ballot(take)));
                 const bool own = part == 0;   // this part keeps the per-window work
                 if constexpr (STATS) {
