@@ -168,8 +168,11 @@ typedef struct {
 #define MG_SCHED_LEARNED 1    /* an MLP predicts the cost of every 64-root
                                  segment; segments above 8x the mean run first,
                                  heaviest first (the costliest split into single
-                                 roots), then the rest in time order from the
-                                 root queues in 64-root chunks (ignores chunk) */
+                                 roots, a root still above 1/32768 of the total
+                                 into up to 16 parts of its first-level
+                                 candidates), then the rest in time order from
+                                 the root queues in 64-root chunks (ignores
+                                 chunk) */
 
 /* Fill opts with the defaults (co-mining, all roots, null stream). */
 void mg_count_opts_init(mg_count_opts *opts);
