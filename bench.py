@@ -37,11 +37,17 @@ def algorithmic_bytes(st, time_bytes, n_roots):
 
 
 def kernel_source_hash():
+    """sha256 of the search kernel's code: its sources with comments and
+    blank space removed (an edit to a comment keeps the hash)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2507_14813_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2507_14813_amd", "csrc", f)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()
 
 

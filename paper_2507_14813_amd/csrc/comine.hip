@@ -19,13 +19,25 @@
 //     t_prev < t <= t_first + delta, found by bisection.  Children that read
 //     the same list (same direction, same anchor vertex) form one group and
 //     share one scan of the window.
-//   * Up to 64 non-empty windows at a time are expanded as one flat candidate
-//     range: lane i takes candidate c + i, finds its window from a 64-bit mask
-//     of window ends (LDS flags + ballot + popcount), reads one adjacency
-//     entry, finds which bound motif vertex it hits with predicated compares,
-//     picks the reached child from the group record (which also carries the
-//     child's motif id), credits LDS counters, and compacts the survivors that
-//     still have children into the next level's buffer with ballot + mbcnt.
+//   * Windows are found from other windows where possible: a root's windows
+//     in out(a) and in(b) start just past the root edge's own list position,
+//     and a deeper window on a list of the root's two vertices lies inside the
+//     root's window on that list (kept in LDS), so it needs a short bisection
+//     and no search for its end.  Below the first level, the pairs on such
+//     lists are taken before the others, so the lanes of one pass run
+//     bisections of similar length.
+//   * A window whose children all end a motif is counted, not expanded: one
+//     equality count per bound vertex (the list's own anchor left out), the
+//     new-vertex child taking the rest; a short one by its own lane, a long
+//     one by the whole wave with ballots.
+//   * The other non-empty windows, up to 64 at a time, are expanded as one
+//     flat candidate range: lane i takes candidate c + i, finds its window
+//     from a 64-bit mask of window ends (LDS flags + ballot + popcount), reads
+//     one adjacency entry, finds which bound motif vertex it hits with
+//     predicated compares, picks the reached child from the group record
+//     (which also carries the child's motif id), credits LDS counters, and
+//     compacts the survivors that still have children into the next level's
+//     buffer with ballot + mbcnt.
 //   * When the next level's buffer holds 64 or more partial matches it is
 //     expanded at once (depth first over batches), so LDS use is bounded by
 //     the motif length, not by the size of the search tree.
