@@ -291,8 +291,10 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
     // root level every entry has the root's groups).  Below it the pairs are
     // taken in two classes: groups on a list of motif vertex 0 or 1 (windows
     // found inside the root's windows: short bisections) first, then the
-    // others, so that the lanes of one pass do bisections of similar length.
-    uint32_t P = 0, P1 = 0, cls = 0;
+    // others, so that the lanes of one pass do bisections of similar length
+    // (pairs are numbered over both classes: the first P0 are of the first, so
+    // only the pass across the boundary mixes them).
+    uint32_t P = 0, P0 = 0, P1 = 0;
     const uint32_t root_ng = (inode[0] >> 20) & 63u;
     if constexpr (L == 1) {
         P = nA * root_ng;
@@ -305,15 +307,16 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                 n0 = w >> 26;
                 n1 = ((w >> 20) & 63u) - n0;
             }
-            const uint32_t i0 = incl_scan32(n0, lane) + P;
+            const uint32_t i0 = incl_scan32(n0, lane) + P0;
             const uint32_t i1 = incl_scan32(n1, lane) + P1;
             if (x < nA) {
                 A.pincl[x] = (uint16_t)i0;
                 A.pincl1[x] = (uint16_t)i1;
             }
-            P = lane_value(i0, kWave - 1);
+            P0 = lane_value(i0, kWave - 1);
             P1 = lane_value(i1, kWave - 1);
         }
+        P = P0 + P1;
         wave_sync();
     }
 
@@ -326,13 +329,6 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
     for (;;) {
         bool done = false;
         if (cc >= T) {
-            if constexpr (L > 1) {
-                if (pc >= P && cls == 0) {   // on to the second class of pairs
-                    cls = 1;
-                    P = P1;
-                    pc = 0;
-                }
-            }
             if (pc >= P) {
                 done = true;
             } else {
@@ -348,16 +344,18 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                         g = (inode[0] & 0xfffffu) + (pi - lo * root_ng);
                         tp = A.tfirst[lo];
                     } else {
-                        const uint16_t *pin = cls ? A.pincl1 : A.pincl;
+                        const bool c1 = pi >= P0;   // second class
+                        const uint32_t pj = c1 ? pi - P0 : pi;
+                        const uint16_t *pin = c1 ? A.pincl1 : A.pincl;
                         uint32_t n = nA;
                         while (n > 0) {
                             const uint32_t h = n >> 1;
-                            if (pin[lo + h] <= pi) { lo += h + 1; n -= h + 1; }
+                            if (pin[lo + h] <= pj) { lo += h + 1; n -= h + 1; }
                             else n = h;
                         }
                         const uint32_t before = lo ? pin[lo - 1] : 0u;
                         const uint32_t w = inode[A.node[lo]];
-                        g = (w & 0xfffffu) + (cls ? (w >> 26) : 0u) + (pi - before);
+                        g = (w & 0xfffffu) + (c1 ? (w >> 26) : 0u) + (pj - before);
                         tp = A.tprev[lo];
                     }
                     x = lo;
