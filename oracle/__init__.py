@@ -112,13 +112,15 @@ def count_many(src, dst, t, n_nodes, motifs, delta, roots=None, threads=0):
 
 
 class OracleGraph:
-    """A graph loaded (sorted, adjacency built) once for many oracle counts."""
+    """A graph loaded (sorted, adjacency built) once for many oracle counts.
 
-    def __init__(self, src, dst, t, n_nodes):
+    ``mutant`` > 0 loads a library with a planted mistake (tests only)."""
+
+    def __init__(self, src, dst, t, n_nodes, mutant=0):
         src = np.ascontiguousarray(src, dtype=np.int32)
         dst = np.ascontiguousarray(dst, dtype=np.int32)
         t = np.ascontiguousarray(t, dtype=np.int64)
-        self._lib = _load()
+        self._lib = _load(mutant)
         self._h = self._lib.oracle_graph_new(len(src), _ptr(src), _ptr(dst), _ptr(t),
                                              int(n_nodes))
         if not self._h:

@@ -42,3 +42,51 @@ def count(src, dst, t, motif, delta, roots=None):
         if is_match([E[i] for i in comb], motif, delta):
             c += 1
     return c
+
+
+def _sorted_edges(src, dst, t):
+    order = sorted(range(len(t)), key=lambda i: (int(t[i]), i))
+    return [(int(src[i]), int(dst[i]), int(t[i])) for i in order]
+
+
+def partial_matches(E, motif, delta, root):
+    """Every match of ``motif`` whose first edge is position ``root`` of the
+    time-sorted edge list E, as a list of edge-position tuples (the definition
+    applied to every subset of later edges)."""
+    k = len(motif)
+    out = []
+    later = range(root + 1, len(E))
+    for rest in itertools.combinations(later, k - 1):
+        tup = (root,) + rest
+        if is_match([E[i] for i in tup], motif, delta):
+            out.append(tup)
+    return out
+
+
+def window_entries(src, dst, t, motif, delta):
+    """Per root and per motif edge j >= 1: the number of list entries with
+    t_prev < t <= t_first + delta summed over the matches of the first j edges
+    from that root, where the list is chosen by the rule the oracle reads into
+    Algorithm 1: the out-edges of the graph vertex bound to u_j if u_j is
+    bound, else the in-edges of the vertex bound to v_j if v_j is bound, else
+    every edge.  Lists hold every edge, self-loops included.  Returns an
+    (n_edges x k) list of lists (column 0 stays 0)."""
+    E = _sorted_edges(src, dst, t)
+    k = len(motif)
+    out = [[0] * k for _ in E]
+    for r in range(len(E)):
+        for j in range(1, k):
+            for tup in partial_matches(E, motif[:j], delta, r):
+                phi = {}
+                for i, (u, v) in zip(tup, motif[:j]):
+                    phi[u], phi[v] = E[i][0], E[i][1]
+                t_prev, t_first = E[tup[-1]][2], E[tup[0]][2]
+                u, v = motif[j]
+                if u in phi:
+                    lst = [e for e in E if e[0] == phi[u]]
+                elif v in phi:
+                    lst = [e for e in E if e[1] == phi[v]]
+                else:
+                    lst = E
+                out[r][j] += sum(1 for e in lst if t_prev < e[2] <= t_first + delta)
+    return out

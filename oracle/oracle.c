@@ -46,7 +46,9 @@
 /* Planted mistakes, compiled only into separate test libraries to show that
  * the pins catch them: 1 admits equal timestamps, 2 drops injectivity for new
  * vertices, 3 makes the window exclusive, 4 measures the window from the
- * previous edge.  0 (the default) is the oracle. */
+ * previous edge, 5 logs window entries only when they pass the structural
+ * filter, 6 logs a partial match before its structural filter.  0 (the
+ * default) is the oracle. */
 #ifndef ORACLE_MUTANT
 #define ORACLE_MUTANT 0
 #endif
@@ -113,7 +115,8 @@ static void match_edge(or_ctx *c, int j, int64_t t_prev) {
         int64_t e = ids ? ids[p] : p;
         int64_t te = g->t[e];
         if (te > tmax || (ORACLE_MUTANT == 3 && te == tmax)) break;  /* window */
-        if (c->win) c->win[j]++;
+        if (c->win && ORACLE_MUTANT != 5) c->win[j]++;
+        if (c->level && ORACLE_MUTANT == 6) c->level[j]++;
         int32_t s = g->src[e], d = g->dst[e];
         /* structural filter */
         if (ug >= 0 && s != ug) continue;
@@ -124,7 +127,8 @@ static void match_edge(or_ctx *c, int j, int64_t t_prev) {
         int new_u = (ug < 0), new_v = (vg < 0);
         if (new_u) c->m2g[um] = s;
         if (new_v) c->m2g[vm] = d;
-        if (c->level) c->level[j]++;
+        if (c->win && ORACLE_MUTANT == 5) c->win[j]++;
+        if (c->level && ORACLE_MUTANT != 6) c->level[j]++;
         match_edge(c, j + 1, te);
         if (new_u) c->m2g[um] = -1;
         if (new_v) c->m2g[vm] = -1;

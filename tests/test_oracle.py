@@ -168,3 +168,123 @@ def test_pins_catch_planted_mistakes(oracle_mod, golden_examples, mutant):
     for m in _tiny_motifs()[:40]:
         diff += oracle_mod.count(s, d, t, 5, m, 3, mutant=mutant) != brute.count(s, d, t, m, 3)
     assert diff > 0
+
+
+def _union_connected(pairs):
+    """Whether the undirected union of the edges is one connected piece."""
+    parent = {}
+
+    def find(x):
+        while parent.setdefault(x, x) != x:
+            x = parent[x]
+        return x
+    for a, b in pairs:
+        parent[find(a)] = find(b)
+    return len({find(x) for e in pairs for x in e}) == 1
+
+
+def _window_motifs():
+    ms = []
+    for k in (1, 2, 3):
+        ms += W.enumerate_motifs(k, 2 * k, connected=False)
+    rng = np.random.default_rng(17)
+    four = W.enumerate_motifs(4, 5, connected=False)
+    return ms + [four[i] for i in rng.choice(len(four), 12, replace=False)]
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_window_and_level_logs_match_brute_force(oracle_mod, seed):
+    """The per-root logs the GPU statistics and the scheduler's cost label are
+    judged by: window entries per motif edge (the list chosen by the oracle's
+    candidate rule, entries with t_prev < t <= t_first + delta, summed over the
+    partial matches of the preceding edges) and partial matches per level,
+    both recomputed by enumerating edge subsets against the definition."""
+    rng = np.random.default_rng(300 + seed)
+    n = int(rng.integers(3, 7))
+    s, d, t = tiny_graph(rng, n, int(rng.integers(8, 12)), 8, self_loops=seed == 1)
+    og = oracle_mod.OracleGraph(s, d, t, n)
+    for m in _window_motifs():
+        for delta in (0, 3, BIG):
+            tot, lv, wn, wr = og.count(list(m), delta, level=True, windows=True,
+                                       windows_per_root=True)
+            want_w = np.array(brute.window_entries(s, d, t, m, delta), dtype=np.uint64)
+            assert np.array_equal(wr, want_w), (m, delta)
+            assert np.array_equal(wn, want_w.sum(0)), (m, delta)
+            for j in range(len(m)):
+                col = [brute.count(s, d, t, m[:j + 1], delta, roots=[r]) for r in range(len(s))]
+                assert lv[:, j].tolist() == col, (m, delta, j)
+            assert int(lv[:, -1].sum()) == tot
+
+
+def test_search_node_identity(oracle_mod):
+    """Per-motif search nodes minus co-mined search nodes equals the sum over
+    shared prefixes p of (multiplicity(p) - 1) * count(p).  Per-motif nodes come
+    from the oracle's level logs; prefix counts and multiplicities from brute
+    force and the motif set."""
+    rng = np.random.default_rng(41)
+    s, d, t = tiny_graph(rng, 6, 22, 14, self_loops=True)
+    motifs = list(W.CONFIG1_MOTIFS) + W.random_extension_motifs(10, (2, 3, 4), 5, 44)
+    delta = 6
+    og = oracle_mod.OracleGraph(s, d, t, 6)
+    mult = {}
+    for m in motifs:
+        for j in range(1, len(m) + 1):
+            mult[tuple(m[:j])] = mult.get(tuple(m[:j]), 0) + 1
+    cnt = {p: brute.count(s, d, t, list(p), delta) for p in mult}
+    per_motif = 0
+    for m in motifs:
+        _, lv = og.count(list(m), delta, level=True)
+        per_motif += int(lv.sum())
+    comined = sum(cnt.values())
+    shared = sum((mult[p] - 1) * cnt[p] for p in mult)
+    assert per_motif - comined == shared
+    assert shared > 0 and any(v > 1 for v in mult.values())
+
+
+@pytest.mark.parametrize("delta", [5, 12])
+def test_partition_identity_908_connected(oracle_mod, delta):
+    """The 68 connected 3-edge and 840 connected 4-edge motifs on <= 4
+    vertices partition the delta-window triples and quadruples whose union is
+    connected, spans <= 4 vertices and has no self-loop (each such tuple has
+    exactly one first-appearance form); counted by an independent enumerator
+    over edge subsets."""
+    three = [m for m in W.enumerate_motifs(3, 4, connected=False) if _union_connected(m)]
+    four = [m for m in W.enumerate_motifs(4, 4, connected=False) if _union_connected(m)]
+    assert (len(three), len(four)) == (68, 840)
+    rng = np.random.default_rng(55)
+    s, d, t = tiny_graph(rng, 5, 34, 30, self_loops=True)
+    o = np.lexsort((np.arange(len(t)), t))
+    s, d, t = s[o], d[o], t[o]
+    og = oracle_mod.OracleGraph(s, d, t, 5)
+    for k, ms in ((3, three), (4, four)):
+        tuples = 0
+        for c in itertools.combinations(range(len(t)), k):
+            ts = t[list(c)]
+            if not np.all(ts[1:] > ts[:-1]) or ts[-1] - ts[0] > delta:
+                continue
+            pairs = [(int(s[i]), int(d[i])) for i in c]
+            if any(a == b for a, b in pairs) or len({x for e in pairs for x in e}) > 4:
+                continue
+            tuples += _union_connected(pairs)
+        got = sum(og.count(list(m), delta) for m in ms)
+        assert got == tuples and tuples > 0, (k, got, tuples)
+
+
+@pytest.mark.parametrize("mutant", [5, 6])
+def test_log_pins_catch_planted_mistakes(oracle_mod, mutant):
+    """Mistakes that leave every count intact but corrupt a log (window entries
+    logged after the structural filter; partial matches logged before it) are
+    caught by the brute-force log pins."""
+    rng = np.random.default_rng(301)
+    n = 5
+    s, d, t = tiny_graph(rng, n, 11, 8, self_loops=True)
+    og = oracle_mod.OracleGraph(s, d, t, n, mutant=mutant)
+    caught = False
+    for m in _window_motifs()[:40]:
+        tot, lv, wr = og.count(list(m), 3, level=True, windows_per_root=True)
+        assert tot == brute.count(s, d, t, m, 3)        # counts stay right
+        want_w = np.array(brute.window_entries(s, d, t, m, 3), dtype=np.uint64)
+        want_l = [[brute.count(s, d, t, m[:j + 1], 3, roots=[r]) for j in range(len(m))]
+                  for r in range(len(s))]
+        caught |= not np.array_equal(wr, want_w) or lv.tolist() != want_l
+    assert caught
