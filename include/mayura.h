@@ -151,7 +151,37 @@ typedef struct {
     int32_t sample;           /* MG_SCHED_LEARNED: the model scores one root in
                                  `sample` of every 64-root segment (a power of
                                  two, 1..64; 0 = default 1) */
+    /* Stopping and resuming (the counterpart of the paper's epoch contexts,
+     * section 4.5, which let a search be suspended and picked up again).
+     * Every wave reads `stop` and takes a claim from the budget before it
+     * claims a chunk of roots; a chunk once claimed is searched to the end.
+     * So a launch that stops has searched a prefix of every root queue, and
+     * `cursor` records those prefixes.  Supported with MG_MODE_COMINE and
+     * MG_SCHED_PLAIN only. */
+    const int32_t *stop;      /* NULL, or a flag in host-pinned (hipHostMalloc)
+                                 or device memory: non-zero = claim no more
+                                 chunks.  The caller may set it while the call
+                                 runs. */
+    int64_t max_chunks;       /* 0 = no limit, else claim at most this many chunks
+                                 in this call (claims that find a queue empty
+                                 count too) */
+    struct mg_cursor *cursor; /* NULL, or in/out resume point (below) */
 } mg_count_opts;
+
+/* Resume point of a stopped count.  Initialise with mg_cursor_init; pass the
+ * same cursor, graph, tree, roots, chunk and queues to every call of one
+ * count.  Each call's counts are those of the roots it searched, so the sum
+ * over the calls until `done` is the full count (and likewise stats and
+ * root_cost). */
+#define MG_CURSOR_QUEUES 8
+typedef struct mg_cursor {
+    uint64_t head[MG_CURSOR_QUEUES]; /* roots already searched from each root queue */
+    int64_t n_roots;          /* roots of the count the cursor belongs to */
+    int32_t chunk, queues;    /* the settings it was made with (resolved defaults) */
+    int32_t started;          /* 0 = fresh: start from the first root */
+    int32_t done;             /* out: 1 once every root has been searched */
+} mg_cursor;
+void mg_cursor_init(mg_cursor *c);
 
 /* mg_count_opts.stats entries; every one is independent of the schedule */
 #define MG_STAT_WIN_LIST 0   /* windows read from a per-vertex adjacency list */
@@ -202,6 +232,12 @@ typedef struct mg_model mg_model;  /* opaque */
 int mg_model_create(uint64_t seed, mg_model **out);
 int mg_model_get_weights(const mg_model *m, float *w /* MG_MODEL_PARAMS */);
 int mg_model_set_weights(mg_model *m, const float *w /* MG_MODEL_PARAMS */);
+/* Adam's first and second moments (MG_MODEL_PARAMS floats each, host; either
+ * may be NULL), in the parameter layout above.  After one step from fresh
+ * moments (mg_model_create or mg_model_set_weights), m1 = (1 - 0.9) * g and
+ * m2 = (1 - 0.999) * g^2 for the minibatch gradient g of the mean squared
+ * error, so the backward pass can be read back exactly. */
+int mg_model_get_moments(const mg_model *m, float *m1, float *m2);
 void mg_model_destroy(mg_model *m);
 /* Features of roots (positions in time order; NULL = all n_edges roots) into
  * feats (host, n x MG_NFEATURES): scaled log1p of the out/in degrees of both

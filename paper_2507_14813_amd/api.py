@@ -54,7 +54,20 @@ class CountOpts(ctypes.Structure):
                 ("elapsed_ms", ctypes.POINTER(ctypes.c_float)),
                 ("stats", ctypes.c_void_p), ("sched", ctypes.c_int32),
                 ("leaf_scan", ctypes.c_int32), ("model", ctypes.c_void_p),
-                ("root_cost", ctypes.c_void_p), ("sample", ctypes.c_int32)]
+                ("root_cost", ctypes.c_void_p), ("sample", ctypes.c_int32),
+                ("stop", ctypes.c_void_p), ("max_chunks", ctypes.c_int64),
+                ("cursor", ctypes.c_void_p)]
+
+
+class Cursor(ctypes.Structure):
+    """Resume point of a stopped count (``mg_cursor``)."""
+    _fields_ = [("head", ctypes.c_uint64 * 8), ("n_roots", ctypes.c_int64),
+                ("chunk", ctypes.c_int32), ("queues", ctypes.c_int32),
+                ("started", ctypes.c_int32), ("done", ctypes.c_int32)]
+
+    def __init__(self):
+        super().__init__()
+        lib().mg_cursor_init(ctypes.byref(self))
 
 
 STAT_NAMES = ("win_list", "win_all", "ent_list", "ent_all", "push", "credit", "roots")
@@ -118,10 +131,13 @@ def lib():
         L.mg_count_opts_init.argtypes = [ctypes.POINTER(CountOpts)]
         L.mg_count_opts_init.restype = None
         L.mg_count.argtypes = [p, p, ctypes.POINTER(CountOpts), p]
+        L.mg_cursor_init.argtypes = [p]
+        L.mg_cursor_init.restype = None
         L.mg_last_error.restype = ctypes.c_char_p
         L.mg_model_create.argtypes = [ctypes.c_uint64, ctypes.POINTER(p)]
         L.mg_model_get_weights.argtypes = [p, p]
         L.mg_model_set_weights.argtypes = [p, p]
+        L.mg_model_get_moments.argtypes = [p, p, p]
         L.mg_model_destroy.argtypes = [p]
         L.mg_model_destroy.restype = None
         L.mg_root_features.argtypes = [p, p, p, i64, p]
@@ -137,7 +153,7 @@ def lib():
         for f in ("mg_set_allocator", "mg_graph_create", "mg_graph_info",
                   "mg_tree_create", "mg_tree_info", "mg_count", "mg_batch_create",
                   "mg_batch_count", "mg_batch_info", "mg_model_create", "mg_model_get_weights",
-                  "mg_model_set_weights", "mg_root_features", "mg_model_predict",
+                  "mg_model_set_weights", "mg_model_get_moments", "mg_root_features", "mg_model_predict",
                   "mg_model_train"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
@@ -263,7 +279,7 @@ class Tree:
 
 def count(graph: Graph, tree: Tree, mode="comine", roots=None, blocks=0, chunk=0,
           queues=0, stream=None, timed=False, stats=False, root_cost=False, model=None,
-          leaf_scan=0, sample=0):
+          leaf_scan=0, sample=0, stop=None, max_chunks=0, cursor=None):
     """Exact count per motif (``mg_count``), in the tree's motif order.
 
     ``mode``: "comine" (one search over the MG-Tree) or "per_motif" (one search
@@ -273,6 +289,9 @@ def count(graph: Graph, tree: Tree, mode="comine", roots=None, blocks=0, chunk=0
     uint64 array; with ``timed`` also the device milliseconds; with ``stats``
     also a dict of search statistics; with ``root_cost`` also the per-root
     cost log (uint64 per edge; both run instrumented kernels).
+    ``stop`` (address of an int32 flag in pinned host or device memory),
+    ``max_chunks`` and ``cursor`` (a ``Cursor``, updated in place) stop a
+    count early and resume it; the counts are then those of this call.
     """
     L = lib()
     o = CountOpts()
@@ -287,6 +306,11 @@ def count(graph: Graph, tree: Tree, mode="comine", roots=None, blocks=0, chunk=0
         o.sched = 1
         o.model = model.handle.value
     o.stream = _default_stream(stream)
+    if stop is not None:
+        o.stop = int(stop)
+    o.max_chunks = int(max_chunks)
+    if cursor is not None:
+        o.cursor = ctypes.addressof(cursor)
     r = None
     if roots is not None:
         r = np.ascontiguousarray(roots, dtype=np.int64)
@@ -342,6 +366,13 @@ class Model:
         w = np.ascontiguousarray(w, dtype=np.float32)
         assert w.size == MODEL_PARAMS
         _check(self._L.mg_model_set_weights(self._h, _p(w)))
+
+    def moments(self):
+        """Adam's first and second moments, in the parameter layout."""
+        m1 = np.zeros(MODEL_PARAMS, dtype=np.float32)
+        m2 = np.zeros(MODEL_PARAMS, dtype=np.float32)
+        _check(self._L.mg_model_get_moments(self._h, _p(m1), _p(m2)))
+        return m1, m2
 
     def predict(self, feats):
         f = np.ascontiguousarray(feats, dtype=np.float32).reshape(-1, NFEATURES)

@@ -12,6 +12,24 @@ constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;
 constexpr int kQueues = 8;      // root queues, one per XCD
 constexpr int kQueueStride = 16;  // u64 words between queue heads (own cache line)
+// queue words: kQueues root-queue heads, the work-item queue head, the claim
+// counter of a chunk budget, each kQueueStride words apart
+constexpr int kItemSlot = kQueues;
+constexpr int kBudgetSlot = kQueues + 1;
+constexpr int kQueueSlots = kQueues + 2;
+constexpr int kQueueWords = kQueueSlots * kQueueStride;
+
+// Root queue q of n_queues over n_roots roots holds positions [begin, end):
+// boundaries on multiples of 64 roots, so that 64-root chunks are the
+// scheduler's segments.  Host and device use this one definition.
+__host__ __device__ inline uint32_t queue_begin(uint32_t n_roots, uint32_t n_queues, uint32_t q) {
+    const uint64_t b = ((uint64_t)n_roots * q) / n_queues + 63;
+    const uint32_t r = (uint32_t)(b & ~(uint64_t)63);
+    return r < n_roots ? r : n_roots;
+}
+__host__ __device__ inline uint32_t queue_end(uint32_t n_roots, uint32_t n_queues, uint32_t q) {
+    return q + 1 == n_queues ? n_roots : queue_begin(n_roots, n_queues, q + 1);
+}
 constexpr uint32_t kLeafScanDefault = 256;   // lane-counted leaf window limit
 
 // group direction: which adjacency list holds the candidates
@@ -66,7 +84,12 @@ struct KParams {
     uint32_t n_roots;
     uint32_t chunk;               // roots per queue grab (multiple of 64)
     uint32_t n_queues;            // 1..kQueues root queues
-    unsigned long long *queues;   // kQueues heads at stride kQueueStride, zeroed
+    unsigned long long *queues;   // kQueueWords: queue heads (zeroed, or a resume
+                                  // point) and the claim counter (zeroed)
+    const int32_t *stop;          // NULL, or a flag (host-pinned or device memory)
+                                  // read before every chunk claim: non-zero = claim
+                                  // no more chunks
+    uint32_t max_chunks;          // 0, or the launch claims at most this many chunks
     unsigned long long *counts;   // n_q, zeroed before launch
     unsigned long long *stats;    // NULL, or kStats totals (zeroed before launch)
     unsigned long long *root_cost;  // NULL, or per root edge id: 1 + window entries

@@ -722,7 +722,7 @@ comine_kernel(const KParams<TT> p) {
         const uint32_t n_items = uniform(*p.n_items);
         for (;;) {
             unsigned long long it = 0;
-            if (lane == 0) it = atomicAdd(&p.queues[kQueues * kQueueStride], 1ull);
+            if (lane == 0) it = atomicAdd(&p.queues[kItemSlot * kQueueStride], 1ull);
             it = lane0_u64(it);
             if (it >= n_items) break;
             const uint2 item = p.items[uniform((uint32_t)it)];
@@ -735,21 +735,29 @@ comine_kernel(const KParams<TT> p) {
         }
     }
     // workgroups are dispatched to the XCDs round-robin: start on this XCD's
-    // share of the roots, then take what is left of the others
+    // share of the roots, then take what is left of the others.  A chunk once
+    // claimed is always searched to the end, so after a stop the queue heads
+    // (clamped to the queue lengths) mark exactly the roots searched.
     const uint32_t nq = p.n_queues;
     const uint32_t home = blockIdx.x % nq;
-    for (uint32_t qi = 0; qi < nq; ++qi) {
+    bool stopped = false;
+    for (uint32_t qi = 0; qi < nq && !stopped; ++qi) {
         const uint32_t q = (home + qi) % nq;
-        // queue boundaries on multiples of 64 roots, so that 64-root chunks
-        // are the scheduler's segments
-        const uint32_t qbeg = min(p.n_roots, (uint32_t)(((uint64_t)p.n_roots * q) / nq + 63) & ~63u);
-        const uint32_t qend =
-            q + 1 == nq ? p.n_roots
-                        : min(p.n_roots, (uint32_t)(((uint64_t)p.n_roots * (q + 1)) / nq + 63) & ~63u);
+        const uint32_t qbeg = queue_begin(p.n_roots, nq, q);
+        const uint32_t qend = queue_end(p.n_roots, nq, q);
         for (;;) {
             unsigned long long got = 0;
-            if (lane == 0) got = atomicAdd(&p.queues[q * kQueueStride], (unsigned long long)p.chunk);
+            if (lane == 0) {
+                bool go = true;
+                if (p.stop) go = __hip_atomic_load(p.stop, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_SYSTEM) == 0;
+                if (go && p.max_chunks)
+                    go = atomicAdd(&p.queues[kBudgetSlot * kQueueStride], 1ull) < p.max_chunks;
+                got = go ? atomicAdd(&p.queues[q * kQueueStride], (unsigned long long)p.chunk)
+                         : ~0ull;
+            }
             got = lane0_u64(got);
+            if (got == ~0ull) { stopped = true; break; }
             if (got >= (unsigned long long)(qend - qbeg)) break;
             const uint32_t base = uniform(qbeg + (uint32_t)got);
             if (p.skip && p.skip[base / kWave]) continue;   // searched as an item

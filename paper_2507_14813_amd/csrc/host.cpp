@@ -21,12 +21,13 @@
 
 using mg::kVMax;
 using mg::kKMax;
-// kQueues root-queue heads plus one work-item queue head
 // the learned schedule predicts the cost of one root in this many per segment
 constexpr uint32_t kSampleDefault = 1;
 // most items one root's search is split into by the learned schedule
 constexpr uint32_t kRootParts = 16;
-constexpr size_t kQueueBytes = sizeof(unsigned long long) * (mg::kQueues + 1) * mg::kQueueStride;
+// queue heads (root queues, work items, chunk budget)
+constexpr size_t kQueueBytes = sizeof(unsigned long long) * mg::kQueueWords;
+static_assert(MG_CURSOR_QUEUES == mg::kQueues, "cursor layout");
 
 namespace {
 
@@ -398,25 +399,21 @@ int learned_search(const mg_graph *g, mg_tree *tr, const mg_model *model,
 
 template <typename TT>
 mg::DevGraph<TT> dev_graph(const mg_graph *g);
-
+mg::DevTree dev_tree(const mg_tree *tr);
 template <typename TT>
-int launch_tree(const mg_graph *g, mg_tree *tr, const uint32_t *d_roots, uint32_t n_roots,
-                unsigned long long *d_queues, unsigned long long *d_counts,
-                unsigned long long *d_stats, unsigned long long *d_cost,
-                const mg_count_opts &o, hipStream_t st, float *ms) {
-    mg::KParams<TT> p{};
+TT delta_sat(int64_t delta);
+
+// Kernel parameters of a count over every root of g (the caller may then
+// restrict the roots).
+template <typename TT>
+void fill_params(mg::KParams<TT> &p, const mg_graph *g, const mg_tree *tr, const mg_count_opts &o,
+                 unsigned long long *d_queues, unsigned long long *d_counts,
+                 unsigned long long *d_stats, unsigned long long *d_cost) {
     p.g = dev_graph<TT>(g);
-    p.tree.inode = (const uint32_t *)tr->d_node.ptr;
-    p.tree.grp = (const uint4 *)tr->d_grp.ptr;
-    p.tree.n_q = (int32_t)tr->distinct.size();
-    p.tree.root_q = tr->root_q;
-    p.tree.depth = tr->depth;
-    if (sizeof(TT) == 4)
-        p.delta_sat = (TT)std::min<uint64_t>((uint64_t)tr->delta, 0xffffffffull);
-    else
-        p.delta_sat = (TT)(uint64_t)tr->delta;
-    p.roots = d_roots;
-    p.n_roots = n_roots;
+    p.tree = dev_tree(tr);
+    p.delta_sat = delta_sat<TT>(tr->delta);
+    p.roots = nullptr;
+    p.n_roots = (uint32_t)g->E;
     p.chunk = (uint32_t)(o.chunk > 0 ? o.chunk : 64);
     p.n_queues = (uint32_t)(o.queues > 0 ? o.queues : mg::kQueues);
     p.leaf_scan = o.leaf_scan < 0 ? 0u : (o.leaf_scan == 0 ? mg::kLeafScanDefault
@@ -425,8 +422,29 @@ int launch_tree(const mg_graph *g, mg_tree *tr, const uint32_t *d_roots, uint32_
     p.counts = d_counts;
     p.stats = d_stats;
     p.root_cost = d_cost;
+    p.stop = o.stop;
+    p.max_chunks = (uint32_t)o.max_chunks;
+}
 
-    HIP_TRY(hipMemsetAsync(d_queues, 0, kQueueBytes, st));
+template <typename TT>
+int launch_tree(const mg_graph *g, mg_tree *tr, const uint32_t *d_roots, uint32_t n_roots,
+                unsigned long long *d_queues, unsigned long long *d_counts,
+                unsigned long long *d_stats, unsigned long long *d_cost,
+                const mg_count_opts &o, hipStream_t st, float *ms) {
+    mg::KParams<TT> p{};
+    fill_params<TT>(p, g, tr, o, d_queues, d_counts, d_stats, d_cost);
+    p.roots = d_roots;
+    p.n_roots = n_roots;
+
+    if (o.cursor && o.cursor->started) {
+        // resume: every root queue starts where the last call stopped
+        std::vector<unsigned long long> q(mg::kQueueWords, 0ull);
+        for (int i = 0; i < mg::kQueues; ++i) q[(size_t)i * mg::kQueueStride] = o.cursor->head[i];
+        HIP_TRY(hipMemcpyAsync(d_queues, q.data(), kQueueBytes, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));   // q is released on return
+    } else {
+        HIP_TRY(hipMemsetAsync(d_queues, 0, kQueueBytes, st));
+    }
     if (d_stats) HIP_TRY(hipMemsetAsync(d_stats, 0, sizeof(unsigned long long) * mg::kStats, st));
     HIP_TRY(hipMemsetAsync(d_counts, 0, sizeof(unsigned long long) * p.tree.n_q, st));
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -875,6 +893,13 @@ int mg_model_set_weights(mg_model *m, const float *w) {
     return MG_OK;
 }
 
+int mg_model_get_moments(const mg_model *m, float *m1, float *m2) {
+    if (!m) return fail(MG_EINVAL, "NULL model");
+    if (m1) HIP_TRY(hipMemcpy(m1, m->adam_m.ptr, sizeof(float) * mg::kParams, hipMemcpyDeviceToHost));
+    if (m2) HIP_TRY(hipMemcpy(m2, m->adam_v.ptr, sizeof(float) * mg::kParams, hipMemcpyDeviceToHost));
+    return MG_OK;
+}
+
 void mg_model_destroy(mg_model *m) { delete m; }
 
 int mg_root_features(const mg_graph *g, const mg_tree *tr_c, const int64_t *roots, int64_t n,
@@ -1217,6 +1242,10 @@ int mg_tree_info(const mg_tree *tr, mg_tree_info_t *out) {
 
 void mg_tree_destroy(mg_tree *tr) { delete tr; }
 
+void mg_cursor_init(mg_cursor *c) {
+    if (c) std::memset(c, 0, sizeof *c);
+}
+
 void mg_count_opts_init(mg_count_opts *o) {
     if (!o) return;
     std::memset(o, 0, sizeof *o);
@@ -1242,6 +1271,22 @@ int mg_count(const mg_graph *g, const mg_tree *tr_c, const mg_count_opts *opts,
             return fail(MG_EINVAL, "stats and root_cost are exclusive");
         if (o.sched != MG_SCHED_PLAIN && o.sched != MG_SCHED_LEARNED)
             return fail(MG_EINVAL, "unknown schedule %d", o.sched);
+        if (o.max_chunks < 0 || o.max_chunks > 0xffffffffll)
+            return fail(MG_EINVAL, "max_chunks must be in [0, 2^32)");
+        const bool stoppable = o.stop || o.max_chunks || o.cursor;
+        if (stoppable && (o.mode != MG_MODE_COMINE || o.sched != MG_SCHED_PLAIN))
+            return fail(MG_EINVAL, "stop, max_chunks and cursor need co-mining with the plain schedule");
+        if (o.cursor && o.cursor->started) {
+            const int32_t ch = o.chunk > 0 ? o.chunk : 64, nq = o.queues > 0 ? o.queues : mg::kQueues;
+            const int64_t nr = o.roots ? o.n_roots : g->E;
+            if (o.cursor->n_roots != nr || o.cursor->chunk != ch || o.cursor->queues != nq)
+                return fail(MG_EINVAL, "the cursor belongs to a count with other roots, chunk or queues");
+            for (int q = 0; q < nq; ++q) {
+                const uint32_t len = mg::queue_end((uint32_t)nr, (uint32_t)nq, (uint32_t)q) -
+                                     mg::queue_begin((uint32_t)nr, (uint32_t)nq, (uint32_t)q);
+                if (o.cursor->head[q] > len) return fail(MG_EINVAL, "cursor head %d past its queue", q);
+            }
+        }
         if (o.sched == MG_SCHED_LEARNED) {
             if (!o.model) return fail(MG_EINVAL, "the learned schedule needs a model");
             if (o.roots) return fail(MG_EINVAL, "the learned schedule searches every root");
@@ -1313,6 +1358,7 @@ int mg_count(const mg_graph *g, const mg_tree *tr_c, const mg_count_opts *opts,
 
         std::vector<uint64_t> qcount(tr->distinct.size(), 0);
         float total_ms = 0.f;
+        mg_cursor cur{};
         for (size_t ri = 0; ri < runs.size(); ++ri) {
             mg_tree *t = runs[ri];
             rc = upload_tree(t, dev, st);
@@ -1329,6 +1375,24 @@ int mg_count(const mg_graph *g, const mg_tree *tr_c, const mg_count_opts *opts,
                                              o.elapsed_ms ? &ms : nullptr);
             if (rc) return rc;
             total_ms += ms;
+            if (o.cursor) {
+                std::vector<unsigned long long> q(mg::kQueueWords);
+                HIP_TRY(hipMemcpyAsync(q.data(), d_queues, kQueueBytes, hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipStreamSynchronize(st));
+                const uint32_t nq = o.queues > 0 ? (uint32_t)o.queues : (uint32_t)mg::kQueues;
+                cur.n_roots = n_roots;
+                cur.chunk = o.chunk > 0 ? o.chunk : 64;
+                cur.queues = (int32_t)nq;
+                cur.started = 1;
+                cur.done = 1;
+                for (uint32_t i = 0; i < (uint32_t)mg::kQueues; ++i) {
+                    const uint64_t len = i < nq ? mg::queue_end(n_roots, nq, i) -
+                                                      mg::queue_begin(n_roots, nq, i)
+                                                : 0;
+                    cur.head[i] = std::min<uint64_t>(q[(size_t)i * mg::kQueueStride], len);
+                    if (cur.head[i] < len) cur.done = 0;
+                }
+            }
             std::vector<uint64_t> h(t->distinct.size());
             HIP_TRY(hipMemcpyAsync(h.data(), d_counts, 8 * h.size(), hipMemcpyDeviceToHost, st));
             std::vector<uint64_t> hs(mg::kStats, 0);
@@ -1348,6 +1412,7 @@ int mg_count(const mg_graph *g, const mg_tree *tr_c, const mg_count_opts *opts,
         }
         if (o.elapsed_ms) *o.elapsed_ms = total_ms;
         if (o.stats) std::copy(stats_sum.begin(), stats_sum.end(), o.stats);
+        if (o.cursor) *o.cursor = cur;
         return MG_OK;
     } catch (const std::bad_alloc &) {
         return fail(MG_ENOMEM, "out of host memory");

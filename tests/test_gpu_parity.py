@@ -106,6 +106,60 @@ def test_medium_graph_all_modes(delta):
     assert np.array_equal(api.count(g, tr, roots=roots), oracle_counts(og, ms, delta, roots))
 
 
+def test_stop_and_resume():
+    """A count stopped by a chunk budget and resumed from its cursor until
+    done sums to the oracle's counts and statistics, on every root and on a
+    root subset; a stop flag set before the call searches nothing and leaves
+    the cursor where it was."""
+    import torch
+    s, d, t, n, ms = _medium(seed=3, E=20000, V=60)
+    delta = 25
+    og = OracleGraph(s, d, t, n)
+    g = api.Graph(s, d, t, n)
+    tr = api.Tree(ms, delta)
+    want = oracle_counts(og, ms, delta)
+    _, want_st = api.count(g, tr, stats=True)
+    stop = torch.zeros(1, dtype=torch.int32, device="cuda")
+    pinned = torch.zeros(1, dtype=torch.int32).pin_memory()
+    for roots, budget, queues in ((None, 5, 0), (None, 1, 3), (np.arange(3, len(s), 5), 2, 8)):
+        say("resume", "roots" if roots is not None else "all", budget, queues)
+        exp = want if roots is None else oracle_counts(og, ms, delta, roots)
+        cur = api.Cursor()
+        total = np.zeros(len(ms), np.uint64)
+        st_total = {}
+        calls = 0
+        while not cur.done:
+            flag = pinned if calls % 2 else stop
+            c, st = api.count(g, tr, roots=roots, queues=queues, max_chunks=budget,
+                              stop=flag.data_ptr(), cursor=cur, stats=True)
+            total += c
+            for k, v in st.items():
+                st_total[k] = st_total.get(k, 0) + v
+            calls += 1
+            assert calls < 10000
+            if calls == 2:
+                # a raised flag: nothing is searched and the cursor stays
+                heads = list(cur.head)
+                stop.fill_(1)
+                torch.cuda.synchronize()
+                c0 = api.count(g, tr, roots=roots, queues=queues, stop=stop.data_ptr(),
+                               cursor=cur)
+                assert int(c0.sum()) == 0 and list(cur.head) == heads and not cur.done
+                stop.fill_(0)
+                torch.cuda.synchronize()
+        assert calls > 2
+        assert np.array_equal(total, exp)
+        if roots is None:
+            assert st_total == want_st
+    # a cursor is tied to its count's roots, chunk and queues
+    cur = api.Cursor()
+    api.count(g, tr, max_chunks=1, cursor=cur)
+    with pytest.raises(api.MayuraError, match="MG_EINVAL"):
+        api.count(g, tr, chunk=128, cursor=cur)
+    with pytest.raises(api.MayuraError, match="MG_EINVAL"):
+        api.count(g, tr, mode="per_motif", max_chunks=1)
+
+
 def _trie_expectations(og, motifs, delta):
     """Search statistics the co-mining search must produce, derived from the
     oracle's per-motif counts and window logs: each distinct prefix is matched

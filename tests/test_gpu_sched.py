@@ -72,10 +72,11 @@ def test_mlp_forward_matches_cpu_reference():
     assert np.all(err <= 0.02 + 0.02 * np.abs(want)), err.max()
 
 
-def test_training_step_direction_matches_reference_gradients():
+def test_training_step_matches_reference_gradients():
     """One Adam step from zero moments moves every weight by ~lr against the
-    sign of its gradient; the gradients come from a CPU reference of the
-    backward pass with the kernel's BF16 roundings."""
+    sign of its gradient, and the gradient read back from Adam's moments
+    equals, element by element, a CPU reference of the backward pass with the
+    kernel's BF16 roundings."""
     rng = np.random.default_rng(1)
     m = api.Model(seed=5)
     P0 = m.weights()
@@ -111,6 +112,27 @@ def test_training_step_direction_matches_reference_gradients():
         assert np.all(np.abs(d) <= 1.01 * lr + 1e-7)
     assert total > 1000 and agree >= 0.97 * total, (agree, total)
     assert np.all(P1[16 * 64:32 * 64] == 0)          # padding rows of W1 stay zero
+    # the gradient itself, element by element: after one step from fresh
+    # moments Adam's first moment is (1 - beta1) * g and its second
+    # (1 - beta2) * g^2
+    m1, m2 = m.moments()
+    m1d = dict(zip(("W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4"), unpack(m1)))
+    m2d = dict(zip(("W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4"), unpack(m2)))
+    m1d["W1"], m2d["W1"] = m1d["W1"][:16], m2d["W1"][:16]
+    one_b1 = float(np.float32(1) - np.float32(0.9))
+    one_b2 = float(np.float32(1) - np.float32(0.999))
+    for k, gr in g.items():
+        gr = gr.reshape(-1)
+        got = np.asarray(m1d[k], np.float64).reshape(-1) / one_b1
+        scale = np.abs(gr).max()
+        # BF16 operands (8-bit mantissa) and FP32 accumulation in another
+        # order: a relative L2 error of 2 % and no element off by more than
+        # 5 % of the layer's largest gradient
+        rel = np.linalg.norm(got - gr) / np.linalg.norm(gr)
+        assert rel < 0.02, (k, rel)
+        assert np.all(np.abs(got - gr) <= 0.05 * scale), (k, np.abs(got - gr).max(), scale)
+        sq = np.asarray(m2d[k], np.float64).reshape(-1) / one_b2
+        assert np.allclose(sq, got ** 2, rtol=1e-3, atol=1e-12 * scale ** 2), k
 
 
 def test_features_match_numpy():
