@@ -217,6 +217,29 @@ int mg_count(const mg_graph *g, const mg_tree *tr, const mg_count_opts *opts,
              uint64_t *counts);
 
 /*
+ * mg_count for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same search, with its queue heads, counters and statistics in a static
+ * device array of MG_NOALLOC_SCRATCH_BYTES per GPU (held until the process
+ * ends) instead of memory allocated per call.  Nothing is allocated: no
+ * hipMalloc, hipFree, events or allocator callbacks.
+ *   opts : NULL = defaults.  Accepted: blocks, chunk, queues, stream,
+ *          leaf_scan, stats, stop, max_chunks.  MG_EINVAL for anything that
+ *          needs memory of its own: per-motif mode, the learned schedule,
+ *          roots, root_cost, elapsed_ms, cursor.
+ * The tree's device tables must already exist on the current device (any
+ * earlier mg_count of the tree there creates them), else MG_EINVAL.
+ * MG_EUNSUPPORTED when the tree has more distinct motifs than the array
+ * holds (MG_MAX_QUERIES).  Every call on one GPU shares that GPU's array, so
+ * calls that overlap on one GPU (two threads, or two streams in flight) race
+ * and must be serialised by the caller; each call clears what it uses before
+ * its search and returns after its counts are on the host.
+ */
+#define MG_NOALLOC_SCRATCH_BYTES ((160 + MG_MAX_QUERIES + 8) * 8)   /* 34,112 */
+int mg_count_noalloc(const mg_graph *g, const mg_tree *tr, const mg_count_opts *opts,
+                     uint64_t *counts);
+
+/*
  * Learned root-cost model (not in the paper): a 4-layer MLP, 16 -> 64 -> 64 ->
  * 64 -> 1 with ReLU, BF16 weights and activations, FP32 accumulation (MFMA),
  * that predicts log(1 + candidate edges examined below a root) -- the label

@@ -133,6 +133,7 @@ def lib():
         L.mg_count.argtypes = [p, p, ctypes.POINTER(CountOpts), p]
         L.mg_cursor_init.argtypes = [p]
         L.mg_cursor_init.restype = None
+        L.mg_count_noalloc.argtypes = [p, p, ctypes.POINTER(CountOpts), p]
         L.mg_last_error.restype = ctypes.c_char_p
         L.mg_model_create.argtypes = [ctypes.c_uint64, ctypes.POINTER(p)]
         L.mg_model_get_weights.argtypes = [p, p]
@@ -151,7 +152,7 @@ def lib():
         L.mg_batch_destroy.argtypes = [p]
         L.mg_batch_destroy.restype = None
         for f in ("mg_set_allocator", "mg_graph_create", "mg_graph_info",
-                  "mg_tree_create", "mg_tree_info", "mg_count", "mg_batch_create",
+                  "mg_tree_create", "mg_tree_info", "mg_count", "mg_count_noalloc", "mg_batch_create",
                   "mg_batch_count", "mg_batch_info", "mg_model_create", "mg_model_get_weights",
                   "mg_model_set_weights", "mg_model_get_moments", "mg_root_features", "mg_model_predict",
                   "mg_model_train"):
@@ -336,6 +337,31 @@ def count(graph: Graph, tree: Tree, mode="comine", roots=None, blocks=0, chunk=0
     if root_cost:
         res.append(rcost[:graph.n_edges])
     return res[0] if len(res) == 1 else tuple(res)
+
+
+def count_noalloc(graph: Graph, tree: Tree, blocks=0, chunk=0, queues=0, stream=None,
+                  stats=False, leaf_scan=0, stop=None, max_chunks=0):
+    """``mg_count_noalloc``: co-mining over every root with the library's
+    static device scratch (no device allocation).  The tree must have been
+    counted on this device before.  Returns the uint64 counts, with ``stats``
+    also the statistics dict."""
+    L = lib()
+    o = CountOpts()
+    L.mg_count_opts_init(ctypes.byref(o))
+    o.blocks, o.chunk, o.queues = int(blocks), int(chunk), int(queues)
+    o.leaf_scan = int(leaf_scan)
+    o.stream = _default_stream(stream)
+    if stop is not None:
+        o.stop = int(stop)
+    o.max_chunks = int(max_chunks)
+    st = np.zeros(len(STAT_NAMES), dtype=np.uint64)
+    if stats:
+        o.stats = st.ctypes.data
+    out = np.zeros(tree.n_motifs, dtype=np.uint64)
+    _check(L.mg_count_noalloc(graph.handle, tree.handle, ctypes.byref(o), _p(out)))
+    if stats:
+        return out, {k: int(v) for k, v in zip(STAT_NAMES, st)}
+    return out
 
 
 NFEATURES = 16

@@ -155,6 +155,13 @@ struct BatchParams {
 template <typename TT>
 hipError_t launch_batch(const BatchParams<TT> &bp, int depth, int blocks, hipStream_t stream);
 
+// Device scratch of the count that allocates nothing: queue words, then
+// kMaxQueries counters, then kStats statistics.  One array per device, held
+// until the process ends; *ptr is its address on the current device.
+constexpr int kMaxQueries = 4096;
+constexpr size_t kStaticWords = (size_t)kQueueWords + kMaxQueries + 8;
+hipError_t static_scratch(unsigned long long **ptr);
+
 // p[0..n) = v with a kernel (safe to record into a captured graph)
 hipError_t launch_fill_u64(unsigned long long *p, uint32_t n, unsigned long long v,
                            hipStream_t stream);

@@ -46,6 +46,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "comine.h"
 #include "device_util.h"
@@ -896,6 +897,31 @@ hipError_t launch_batch(const BatchParams<TT> &bp, int depth, int blocks, hipStr
         case 5: return launch_batch_d<TT, 5>(bp, blocks, stream);
         default: return hipErrorInvalidValue;
     }
+}
+
+// The scratch array itself.  In host code its name is a host-side stand-in,
+// never a device address: host code uses only the per-device address that
+// hipGetSymbolAddress returns.
+static_assert(kStats <= 8, "statistics words");
+static __device__ __align__(256) unsigned long long scratch[kStaticWords];
+
+hipError_t static_scratch(unsigned long long **ptr) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static unsigned long long *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *a = nullptr;
+        e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = static_cast<unsigned long long *>(a);
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_fill_u64(unsigned long long *p, uint32_t n, unsigned long long v,

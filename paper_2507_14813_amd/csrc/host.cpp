@@ -28,6 +28,8 @@ constexpr uint32_t kRootParts = 16;
 // queue heads (root queues, work items, chunk budget)
 constexpr size_t kQueueBytes = sizeof(unsigned long long) * mg::kQueueWords;
 static_assert(MG_CURSOR_QUEUES == mg::kQueues, "cursor layout");
+static_assert(MG_MAX_QUERIES == mg::kMaxQueries, "query limit");
+static_assert(MG_NOALLOC_SCRATCH_BYTES == 8 * mg::kStaticWords, "static scratch size");
 
 namespace {
 
@@ -1241,6 +1243,71 @@ int mg_tree_info(const mg_tree *tr, mg_tree_info_t *out) {
 }
 
 void mg_tree_destroy(mg_tree *tr) { delete tr; }
+
+int mg_count_noalloc(const mg_graph *g, const mg_tree *tr, const mg_count_opts *opts,
+                     uint64_t *counts) {
+    try {
+        if (!g || !tr || !counts) return fail(MG_EINVAL, "NULL argument");
+        mg_count_opts o;
+        mg_count_opts_init(&o);
+        if (opts) o = *opts;
+        if (o.mode != MG_MODE_COMINE || o.sched != MG_SCHED_PLAIN || o.roots || o.root_cost ||
+            o.elapsed_ms || o.cursor)
+            return fail(MG_EINVAL, "mg_count_noalloc takes co-mining with the plain schedule over "
+                                   "every root; roots, root_cost, elapsed_ms and cursor need memory");
+        if (o.chunk < 0 || (o.chunk % 64) != 0 || o.chunk > (1 << 16))
+            return fail(MG_EINVAL, "chunk must be a multiple of 64 in [0, 65536]");
+        if (o.queues < 0 || o.queues > mg::kQueues)
+            return fail(MG_EINVAL, "queues must be in [0, %d]", mg::kQueues);
+        if (o.max_chunks < 0 || o.max_chunks > 0xffffffffll)
+            return fail(MG_EINVAL, "max_chunks must be in [0, 2^32)");
+        const size_t nq = tr->distinct.size();
+        if (nq > (size_t)mg::kMaxQueries)
+            return fail(MG_EUNSUPPORTED, "%zu distinct motifs; the static counters hold %d", nq,
+                        mg::kMaxQueries);
+        int dev = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        if (dev != g->device) return fail(MG_EINVAL, "graph lives on device %d, current is %d",
+                                          g->device, dev);
+        if (tr->device != dev || !tr->d_node.ptr)
+            return fail(MG_EINVAL, "the tree has no device tables on device %d yet (count it "
+                                   "with mg_count there once)", dev);
+        unsigned long long *scr = nullptr;
+        HIP_TRY(mg::static_scratch(&scr));
+        unsigned long long *d_queues = scr;
+        unsigned long long *d_counts = scr + mg::kQueueWords;
+        unsigned long long *d_stats = o.stats ? d_counts + mg::kMaxQueries : nullptr;
+        hipStream_t st = (hipStream_t)o.stream;
+        // queue heads, claim counter, counters and statistics start at zero
+        // (a fill kernel, no memset node if the caller captures the stream)
+        HIP_TRY(mg::launch_fill_u64(scr, (uint32_t)mg::kStaticWords, 0ull, st));
+        const uint32_t n_roots = (uint32_t)g->E;
+        if (n_roots > 0) {
+            hipError_t e;
+            if (g->time_bytes == 4) {
+                mg::KParams<uint32_t> p{};
+                fill_params<uint32_t>(p, g, tr, o, d_queues, d_counts, d_stats, nullptr);
+                e = mg::launch_comine<uint32_t>(p, o.blocks, st);
+            } else {
+                mg::KParams<uint64_t> p{};
+                fill_params<uint64_t>(p, g, tr, o, d_queues, d_counts, d_stats, nullptr);
+                e = mg::launch_comine<uint64_t>(p, o.blocks, st);
+            }
+            if (e != hipSuccess)
+                return fail(MG_EDEVICE, "co-mining launch failed: %s", hipGetErrorString(e));
+        }
+        uint64_t h[mg::kMaxQueries];
+        uint64_t hs[mg::kStats];
+        if (nq) HIP_TRY(hipMemcpyAsync(h, d_counts, 8 * nq, hipMemcpyDeviceToHost, st));
+        if (d_stats) HIP_TRY(hipMemcpyAsync(hs, d_stats, sizeof hs, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (int32_t i = 0; i < tr->n_motifs; ++i) counts[i] = h[tr->motif_q[i]];
+        if (o.stats) std::copy(hs, hs + mg::kStats, o.stats);
+        return MG_OK;
+    } catch (...) {
+        return fail(MG_EINTERNAL, "unexpected exception");
+    }
+}
 
 void mg_cursor_init(mg_cursor *c) {
     if (c) std::memset(c, 0, sizeof *c);
