@@ -28,10 +28,19 @@ def log(*a):
 
 
 def algorithmic_bytes(st, time_bytes, n_roots):
-    """Bytes the search must read once: each root's (src, dst, t); each
-    per-vertex window's offset pair; one neighbour id per per-vertex window
-    entry; (src, dst) per whole-list window entry; the time of each partial
-    match kept for a deeper level.  Bisection probes are not counted."""
+    """What the method moves per launch: a 16-byte record per root edge, a
+    16-byte offset pair per window, and per window entry its vertex id and
+    time (8 bytes with 32-bit relative times; a whole-list entry carries two
+    vertex ids).  Bisection probes are not counted."""
+    return (16 * n_roots + 16 * (st["win_list"] + st["win_all"])
+            + (4 + time_bytes) * st["ent_list"] + (8 + time_bytes) * st["ent_all"])
+
+
+def algorithmic_bytes_narrow(st, time_bytes, n_roots):
+    """A narrower model: each root's (src, dst, t); each per-vertex window's
+    offset pair; one neighbour id per per-vertex window entry (the leaf
+    counts read only ids); (src, dst) per whole-list window entry; the time
+    of each partial match kept for a deeper level."""
     return (n_roots * (8 + time_bytes) + st["win_list"] * 8 + st["ent_list"] * 4
             + st["ent_all"] * 8 + st["push"] * time_bytes)
 
@@ -51,12 +60,10 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(n_edges):
-    """HBM bytes per launch of the search kernel from the committed counter
-    summary: FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what
-    the same counter reads for a device copy of known size.  None when the
-    summary is missing, was taken on another workload, or the kernel sources
-    changed since."""
+def counter_record(n_edges):
+    """The committed counter summary of the search kernel on this workload
+    (rocprofv3 --pmc), or None when it is missing, was taken on another
+    workload, or the kernel sources changed since."""
     try:
         with open(COUNTER_SUMMARY) as fh:
             txt = fh.read()
@@ -65,7 +72,20 @@ def measured_traffic(n_edges):
         return None
     if rec.get("kernel_source_sha256") != kernel_source_hash() or rec.get("n_edges") != n_edges:
         return None
+    return rec
+
+
+def measured_traffic(rec):
+    """HBM bytes per launch: FETCH_SIZE and WRITE_SIZE (KiB per dispatch),
+    each scaled by what the same counter reads for a device copy of known
+    size."""
+    if rec is None:
+        return None
     return 1024.0 * (rec["fetch_kib"] * rec["fetch_factor"] + rec["write_kib"] * rec["write_factor"])
+
+
+# one wave64 VALU instruction per CU per clock: 256 CUs at 2.4 GHz
+VALU_PEAK_INSTS_PER_S = 256 * 2.4e9
 
 
 def cpu_baseline(s, d, t, n, motifs, delta, target_s):
@@ -153,26 +173,31 @@ def bench_batched(args):
 
     tb, out = timed_steps(batched, args.steps, args.warmup)
     assert all(np.array_equal(a, r) for a, r in zip(out, ref))
-    tbl, out = timed_steps(bl.count, args.steps, args.warmup)
+    tbl_step, out = timed_steps(bl.count, args.steps, args.warmup)
     assert all(np.array_equal(a, r) for a, r in zip(out, ref))
+    # the learned step includes the cost model's prediction for its plan
+    predict_s = bl.info()["predict_ms"] / 1e3
+    tbl = tbl_step + predict_s
     ts, out = timed_steps(sequential, args.steps, args.warmup)
     assert all(np.array_equal(a, r) for a, r in zip(out, ref))
-    tp, out = timed_steps(lambda: sequential("per_motif"), 1, 0)
+    tp, out = timed_steps(lambda: sequential("per_motif"), 1, 1)
     assert all(np.array_equal(a, r) for a, r in zip(out, ref))
     info = b.info()
+    best = min(tb, tbl)
     return {
-        "metric": "root edges searched/s, learned + batched (64 graphs, one captured launch), "
+        "metric": "root edges searched/s, batched (64 graphs, one captured launch), "
                   "exact counts",
-        "value": E / tbl, "unit": "root edges/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1e3 * tbl, "higher_is_better": True,
+        "value": E / tb, "unit": "root edges/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * tb, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int32/u32, u64 counts",
         "data": "synthetic",
         "config": {"workload": "64 powerlaw graphs, E log-uniform 1e4-2e6 (sum %d), "
                                "4-24 motifs of 2-4 edges each" % E,
                    "n_motifs": int(sum(len(m) for m in wl.motif_sets))},
-        "batched_plain_ms": 1e3 * tb, "sequential_ms": 1e3 * ts, "per_motif_ms": 1e3 * tp,
-        "speedup_vs_batched_plain": tb / tbl, "speedup_vs_sequential": ts / tbl,
-        "speedup_vs_per_motif": tp / tbl,
+        "learned_batched_ms": 1e3 * tbl, "learned_step_ms": 1e3 * tbl_step,
+        "learned_predict_ms": 1e3 * predict_s, "sequential_ms": 1e3 * ts,
+        "per_motif_ms": 1e3 * tp, "speedup_learned_vs_plain_batch": tb / tbl,
+        "speedup_vs_sequential": ts / best, "speedup_vs_per_motif": tp / best,
         "batch": info, "batch_create_s": create_s, "learned_batch_create_s": create_learned_s,
         "train_loss": [float(x) for x in loss],
     }
@@ -227,7 +252,7 @@ def bench_learned(args):
         "held_out_spearman": rho, "train_loss": [float(x) for x in loss], "train_s": train_s,
     }
     if args.per_motif_steps:
-        tpm, c = timed_steps(lambda: api.count(g, tr, mode="per_motif"), 1, 0)
+        tpm, c = timed_steps(lambda: api.count(g, tr, mode="per_motif"), 1, 1)
         assert np.array_equal(c, ref)
         out["per_motif_ms"] = 1e3 * tpm
         out["speedup_vs_per_motif"] = tpm / tl_
@@ -235,60 +260,81 @@ def bench_learned(args):
 
 
 def bench_sweep(args):
-    """Config 5: one 200M-edge graph, 48 motifs of 3-5 edges, delta swept over
-    {900, 3600, 21600}: the three trees in one learned + batched launch vs
-    three plain launches vs per-motif mining."""
+    """Config 5: one 200M-edge graph, 48 motifs of 3-5 edges, windows
+    {900, 3600, 21600}: all three windows counted in one search (a
+    multi-window tree), against three searches, the learned + batched launch
+    and per-motif mining; counts checked against the oracle on roots drawn
+    uniformly and from the heaviest 1 % of the cost log."""
     import numpy as np
     import torch
     from paper_2507_14813_amd import api, workloads as W
+    import oracle
     t0 = time.perf_counter()
     wl = W.make_config(5, scale=args.scale, progress=lambda m: log("generator:", m))
     s, d, t, n = wl.graphs[0]
     ms = wl.motif_sets[0]
+    windows = list(wl.deltas)
     E = len(s)
     log("generated %d edges in %.1f s" % (E, time.perf_counter() - t0))
     g = api.Graph(s, d, t, n, sorted_by_t=True)
+    trees = [api.Tree(ms, dl) for dl in windows]
+    tm = api.Tree(ms, windows)
+    ref = np.stack([api.count(g, tr) for tr in trees])
+    # oracle parity on sampled roots (uniform + the heaviest 1 % by cost)
+    _, cost = api.count(g, tm, root_cost=True)
+    rng = np.random.default_rng(5)
+    uni = rng.choice(E, min(E, args.sample_roots), replace=False)
+    top = np.argsort(cost)[-max(1, E // 100):]
+    roots = np.unique(np.concatenate([uni, rng.choice(top, min(len(top), 128), replace=False)]))
+    t0 = time.perf_counter()
+    og = oracle.OracleGraph(s, d, t, n)
+    want = np.array([[og.count(m, w, roots=roots) for m in ms] for w in windows], np.uint64)
+    og.close()
+    oracle_s = time.perf_counter() - t0
+    if not np.array_equal(api.count(g, tm, roots=roots), want):
+        raise SystemExit("config 5: counts on sampled roots differ from the oracle")
+    log("oracle parity on %d sampled roots (%.1f s)" % (len(roots), oracle_s))
     del s, d, t
-    trees = [api.Tree(ms, dl) for dl in wl.deltas]
-    ref = [api.count(g, tr) for tr in trees]
+    t3, out = timed_steps(lambda: [api.count(g, tr) for tr in trees], args.steps, args.warmup)
+    assert np.array_equal(np.stack(out), ref)
+    t1, out = timed_steps(lambda: api.count(g, tm), args.steps, args.warmup)
+    assert np.array_equal(out, ref)
     # model trained on a separately seeded graph of the same recipe, a tenth of the size
     V2, E2 = max(16, n // 10), max(16, E // 10)
     s2, d2, t2 = W.powerlaw_graph(V2, E2, 2.0, 100_000_000, seed=105, burst_cap=32)
     g2 = api.Graph(s2, d2, t2, V2, sorted_by_t=True)
-    rng = np.random.default_rng(0)
-    feats, labels = [], []
-    for tr in trees:
-        _, cost = api.count(g2, tr, root_cost=True)
-        f = api.root_features(g2, tr)
-        live = np.flatnonzero(cost > 0)
-        pick = rng.choice(live, min(len(live), args.train_samples // 3), replace=False)
-        feats.append(f[pick])
-        labels.append(np.log1p(cost[pick]).astype(np.float32))
+    _, cost2 = api.count(g2, tm, root_cost=True)
+    f2 = api.root_features(g2, tm)
+    live = np.flatnonzero(cost2 > 0)
+    pick = rng.choice(live, min(len(live), args.train_samples), replace=False)
     model = api.Model(seed=1)
-    loss = model.train(np.concatenate(feats), np.concatenate(labels), epochs=args.train_epochs,
-                       lr=2e-3, seed=2)
+    loss = model.train(f2[pick], np.log1p(cost2[pick]).astype(np.float32),
+                       epochs=args.train_epochs, lr=2e-3, seed=2)
     log("model loss", np.round(loss, 3))
-    b = api.Batch([g] * len(trees), trees, model=model)
+    b = api.Batch([g], [tm], model=model)
     tl, out = timed_steps(b.count, args.steps, args.warmup)
-    assert all(np.array_equal(a, r) for a, r in zip(out, ref))
-    tp, out = timed_steps(lambda: [api.count(g, tr) for tr in trees], args.steps, args.warmup)
-    assert all(np.array_equal(a, r) for a, r in zip(out, ref))
+    assert np.array_equal(out[0], ref)
+    predict_s = b.info()["predict_ms"] / 1e3
     res = {
-        "metric": "root edges searched/s, learned + batched delta sweep (config 5), exact counts",
-        "value": len(trees) * E / tl, "unit": "root edges/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * tl,
+        "metric": "root edges searched/s, all three windows in one search (config 5), "
+                  "exact counts",
+        "value": E / t1, "unit": "root edges/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * t1,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int32/u32, u64 counts; MLP bf16/fp32", "data": "synthetic",
         "config": {"workload": "powerlaw V=%d E=%d gamma=2.0 span=1e8 s, 48 motifs of 3-5 "
-                               "edges, delta in %s" % (n, E, wl.deltas)},
-        "plain_ms": 1e3 * tp, "speedup_vs_plain": tp / tl, "train_loss": [float(x) for x in loss],
-        "batch": b.info(), "counts_total": [int(r.sum()) for r in ref],
+                               "edges, windows %s" % (n, E, windows)},
+        "three_searches_ms": 1e3 * t3, "speedup_vs_three_searches": t3 / t1,
+        "learned_batched_ms": 1e3 * (tl + predict_s), "learned_batched_step_ms": 1e3 * tl,
+        "learned_predict_ms": 1e3 * predict_s, "speedup_learned_vs_plain": t1 / (tl + predict_s),
+        "train_loss": [float(x) for x in loss], "counts_total": [int(r.sum()) for r in ref],
+        "oracle_sampled_roots": int(len(roots)), "oracle_s": oracle_s,
     }
     if args.per_motif_steps:
-        tpm, out = timed_steps(lambda: [api.count(g, tr, mode="per_motif") for tr in trees], 1, 0)
-        assert all(np.array_equal(a, r) for a, r in zip(out, ref))
+        tpm, out = timed_steps(lambda: api.count(g, tm, mode="per_motif"), 1, 1)
+        assert np.array_equal(out, ref)
         res["per_motif_ms"] = 1e3 * tpm
-        res["speedup_vs_per_motif"] = tpm / tl
+        res["speedup_vs_per_motif"] = tpm / t1
     return res
 
 
@@ -308,6 +354,8 @@ def main():
                          "4: learned schedule; 5: learned + batched delta sweep")
     ap.add_argument("--train-samples", type=int, default=200000)
     ap.add_argument("--train-epochs", type=int, default=6)
+    ap.add_argument("--sample-roots", type=int, default=2048,
+                    help="config 5: uniformly drawn roots checked against the oracle")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -352,7 +400,8 @@ def main():
 
     counts, st = api.count(g, tr, stats=True)
     algo_bytes = algorithmic_bytes(st, gi["time_bytes"], E)
-    log("stats", st, "algorithmic bytes/launch %.3e" % algo_bytes)
+    algo_narrow = algorithmic_bytes_narrow(st, gi["time_bytes"], E)
+    log("stats", st, "algorithmic bytes/launch %.3e (narrow model %.3e)" % (algo_bytes, algo_narrow))
 
     kw = dict(queues=args.queues, chunk=args.chunk)
     for _ in range(args.warmup):
@@ -371,8 +420,11 @@ def main():
     value = E / (wall / args.steps)
     log("co-mine: %.3f ms/step wall, kernel %.3f ms avg" % (ms_step, sum(kms) / len(kms)))
 
-    # per-motif mining on the same GPU: one launch per motif
+    # per-motif mining on the same GPU: one launch per motif (a first untimed
+    # pass builds the per-motif chain trees and warms up)
     pm_ms, pm_wall = [], []
+    if args.per_motif_steps:
+        api.count(g, tr, mode="per_motif", **kw)
     for _ in range(args.per_motif_steps):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -389,7 +441,24 @@ def main():
 
     k_avg_s = sum(kms) / len(kms) / 1e3
     achieved = algo_bytes / k_avg_s / 1e9
-    traffic = measured_traffic(E)
+    rec = counter_record(E)
+    traffic = measured_traffic(rec)
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "algorithmic_bytes_per_launch": algo_bytes,
+                "narrow_model": {"bytes_per_launch": algo_narrow,
+                                 "frac": algo_narrow / k_avg_s / 1e9 / HBM_PEAK_GBS},
+                "kernel_source_sha256": kernel_source_hash()}
+    if rec is not None:
+        roofline["hbm_frac"] = traffic / k_avg_s / 1e9 / HBM_PEAK_GBS
+        if rec.get("tcc_hit") is not None:
+            roofline["l2_hit"] = rec["tcc_hit"] / (rec["tcc_hit"] + rec["tcc_miss"])
+        if rec.get("valu_insts") is not None:
+            # what limits the kernel: VALU issue (counted instructions over the
+            # issue rate of 256 CUs), not HBM bandwidth
+            roofline["limiter"] = "VALU issue"
+            roofline["valu_insts"] = rec["valu_insts"]
+            roofline["valu_issue_frac"] = rec["valu_insts"] / VALU_PEAK_INSTS_PER_S / k_avg_s
     out = {
         "metric": "root edges searched/s + co-mine speedup vs per-motif on GPU, exact counts",
         "value": value,
@@ -414,10 +483,7 @@ def main():
         "per_motif_kernel_ms": sum(pm_ms) / len(pm_ms) if pm_ms else None,
         "paper_context": "paper reports 2.4x (CPU, Xeon 8380) and 1.7x (GPU, A40) average "
                          "co-mining speedups on real graphs",
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": algo_bytes,
-                     "kernel_source_sha256": kernel_source_hash()},
+        "roofline": roofline,
         "stats": st,
         "total_matches": int(counts.sum()),
     }

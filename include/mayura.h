@@ -43,10 +43,13 @@ typedef enum {
 /* compiled limits */
 #define MG_MAX_EDGES_PER_MOTIF 5   /* k <= 5 */
 #define MG_MAX_MOTIF_VERTICES 6    /* distinct motif vertices <= 6 */
-#define MG_MAX_QUERIES 4096        /* distinct motifs per tree */
+#define MG_MAX_QUERIES 4096        /* counters per tree: distinct motifs x windows */
+#define MG_MAX_DELTAS 8            /* windows counted in one search */
 
 /* mg_graph_create flags */
 #define MG_SORTED_BY_T 1u          /* caller promises t is non-decreasing */
+#define MG_DEVICE_INPUT 2u         /* src, dst and t are device pointers (current
+                                      device); they are read on `stream` */
 
 typedef struct mg_graph mg_graph;  /* opaque */
 typedef struct mg_tree mg_tree;    /* opaque */
@@ -64,8 +67,9 @@ int mg_set_allocator(mg_alloc_fn alloc, mg_release_fn release, void *ctx);
 /*
  * Load a temporal graph (paper, section 2.1 "A Temporal Graph"; data loading
  * into a time-sorted adjacency, section 4.2).
- *   src, dst : n_edges vertex ids in [0, n_nodes), host memory
- *   t        : n_edges timestamps, host memory, any order unless
+ *   src, dst : n_edges vertex ids in [0, n_nodes), host memory (device
+ *              memory with MG_DEVICE_INPUT)
+ *   t        : n_edges timestamps, same memory as src, any order unless
  *              MG_SORTED_BY_T is given (then it must be non-decreasing)
  * The edges are stably sorted by t; edge i of the graph is position i of that
  * order and is the i-th root edge.  Self-loops are kept as roots but never
@@ -106,6 +110,22 @@ void mg_graph_destroy(mg_graph *g);
 int mg_tree_create(const int32_t *motif_uv, const int32_t *motif_k,
                    int32_t n_motifs, int64_t delta, mg_tree **out);
 
+/*
+ * One tree for several windows at once (the window sweep of the paper's
+ * evaluation, "Effect of delta", and its appendix table of delta/4 against
+ * 4 delta).  The search runs once, at the largest window; a match whose span
+ * (last time minus first time) is s counts for every window >= s, which is
+ * exact because a match within a window is also within every larger one.
+ *   deltas   : n_deltas windows, each >= 0, any order (duplicates allowed)
+ * mg_count then returns n_deltas * n_motifs counts, window-major:
+ * counts[i * n_motifs + m] is motif m at deltas[i].  mg_tree_create is the
+ * case n_deltas = 1.  Errors as mg_tree_create; MG_EUNSUPPORTED beyond
+ * MG_MAX_DELTAS windows or MG_MAX_QUERIES counters.
+ */
+int mg_tree_create_multi(const int32_t *motif_uv, const int32_t *motif_k,
+                         int32_t n_motifs, const int64_t *deltas, int32_t n_deltas,
+                         mg_tree **out);
+
 typedef struct {
     int32_t n_motifs;        /* as given */
     int32_t n_distinct;      /* after relabelling and de-duplication */
@@ -114,7 +134,8 @@ typedef struct {
     int32_t depth;           /* longest motif, in edges */
     int32_t root_edges;      /* |C_root|, edges common to every motif */
     double similarity;       /* SM, paper section 5: 1 - n_prefixes / sum of motif edges */
-    int64_t delta;
+    int64_t delta;           /* the largest window */
+    int32_t n_deltas;        /* windows as given */
 } mg_tree_info_t;
 int mg_tree_info(const mg_tree *tr, mg_tree_info_t *out);
 void mg_tree_destroy(mg_tree *tr);
@@ -163,8 +184,8 @@ typedef struct {
                                  chunks.  The caller may set it while the call
                                  runs. */
     int64_t max_chunks;       /* 0 = no limit, else claim at most this many chunks
-                                 in this call (claims that find a queue empty
-                                 count too) */
+                                 in this call (and at least one while roots are
+                                 left, unless stopped by the flag) */
     struct mg_cursor *cursor; /* NULL, or in/out resume point (below) */
 } mg_count_opts;
 
@@ -210,7 +231,8 @@ void mg_count_opts_init(mg_count_opts *opts);
 /*
  * Count every motif of the tree in the graph (paper, Algorithm 3).
  *   opts   : NULL = defaults
- *   counts : host, n_motifs entries in the caller's motif order
+ *   counts : host, n_deltas * n_motifs entries: for each window in the
+ *            caller's order, the motifs in the caller's motif order
  * The result is exact and independent of every scheduling option.
  */
 int mg_count(const mg_graph *g, const mg_tree *tr, const mg_count_opts *opts,
@@ -297,17 +319,22 @@ typedef struct {
     int32_t use_graph;        /* 1 = capture the step and replay it (default), 0 = plain launches */
     int32_t reserved;
     void *stream;             /* hipStream_t the steps run on (NULL = null stream) */
-    const struct mg_model *model;  /* optional: items are every job's 64-root segments
-                                      ordered by predicted cost across the batch,
-                                      costly ones split into single roots
-                                      (item_roots is then ignored) */
+    const struct mg_model *model;  /* optional: the model predicts every job's
+                                      64-root segments at creation; segments above
+                                      8x the mean run first, heaviest first (the
+                                      costliest as one item per root, a root above
+                                      1/(128 x CUs) of the total in up to 16 parts
+                                      of its first-level candidates), then every
+                                      other segment in job order (largest graph
+                                      first) and time order (item_roots is then
+                                      ignored) */
 } mg_batch_opts;
 void mg_batch_opts_init(mg_batch_opts *opts);
 int mg_batch_create(const mg_graph *const *graphs, const mg_tree *const *trees, int32_t n,
                     const mg_batch_opts *opts, mg_batch **out);
 
-/* One step.  counts: host, sum of the trees' n_motifs, concatenated in job
- * order, each tree in its caller's motif order.  elapsed_ms (optional): device
+/* One step.  counts: host, sum of the trees' n_deltas * n_motifs,
+ * concatenated in job order, each tree laid out as mg_count lays it out.  elapsed_ms (optional): device
  * time of the step from events on the batch's stream. */
 int mg_batch_count(mg_batch *b, uint64_t *counts, float *elapsed_ms);
 
@@ -322,9 +349,21 @@ typedef struct {
     int32_t depth;            /* deepest tree */
     float tuned_ms;           /* best step time seen by the autotuner (0 if none) */
     int32_t learned;          /* 1 when items come from the cost model */
+    float predict_ms;         /* wall time of the cost model at creation: features,
+                                 MLP and ordering of the items (0 without a model) */
 } mg_batch_info_t;
 int mg_batch_info(const mg_batch *b, mg_batch_info_t *out);
 void mg_batch_destroy(mg_batch *b);
+
+/*
+ * One-shot batch: mg_batch_create, one mg_batch_count and mg_batch_destroy
+ * in one call, for a set of jobs counted once.  A plan that is counted once
+ * gains nothing from a captured graph or from autotuning (which times
+ * several steps), so use_graph is ignored and item_roots 0 means 64.
+ * counts: as mg_batch_count.
+ */
+int mg_count_batch(const mg_graph *const *graphs, const mg_tree *const *trees, int32_t n,
+                   const mg_batch_opts *opts, uint64_t *counts);
 
 /* Thread-local description of the last failure on this thread. */
 const char *mg_last_error(void);

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libmayura.so")
 MODE_COMINE = 0
 MODE_PER_MOTIF = 1
 SORTED_BY_T = 1
+DEVICE_INPUT = 2
 
 _STATUS = {0: "MG_OK", -1: "MG_EINVAL", -2: "MG_ENOMEM", -3: "MG_EDEVICE",
            -4: "MG_EUNSUPPORTED", -5: "MG_EINTERNAL"}
@@ -43,7 +44,8 @@ class TreeInfo(ctypes.Structure):
     _fields_ = [("n_motifs", ctypes.c_int32), ("n_distinct", ctypes.c_int32),
                 ("n_prefixes", ctypes.c_int32), ("n_nodes", ctypes.c_int32),
                 ("depth", ctypes.c_int32), ("root_edges", ctypes.c_int32),
-                ("similarity", ctypes.c_double), ("delta", ctypes.c_int64)]
+                ("similarity", ctypes.c_double), ("delta", ctypes.c_int64),
+                ("n_deltas", ctypes.c_int32)]
 
 
 class CountOpts(ctypes.Structure):
@@ -84,7 +86,8 @@ class BatchInfo(ctypes.Structure):
                 ("total_roots", ctypes.c_int64), ("n_items", ctypes.c_int64),
                 ("item_roots", ctypes.c_int32), ("blocks", ctypes.c_int32),
                 ("graph_captured", ctypes.c_int32), ("depth", ctypes.c_int32),
-                ("tuned_ms", ctypes.c_float), ("learned", ctypes.c_int32)]
+                ("tuned_ms", ctypes.c_float), ("learned", ctypes.c_int32),
+                ("predict_ms", ctypes.c_float)]
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
@@ -125,6 +128,7 @@ def lib():
         L.mg_graph_destroy.argtypes = [p]
         L.mg_graph_destroy.restype = None
         L.mg_tree_create.argtypes = [p, p, i32, i64, ctypes.POINTER(p)]
+        L.mg_tree_create_multi.argtypes = [p, p, i32, p, i32, ctypes.POINTER(p)]
         L.mg_tree_info.argtypes = [p, ctypes.POINTER(TreeInfo)]
         L.mg_tree_destroy.argtypes = [p]
         L.mg_tree_destroy.restype = None
@@ -151,9 +155,10 @@ def lib():
         L.mg_batch_info.argtypes = [p, ctypes.POINTER(BatchInfo)]
         L.mg_batch_destroy.argtypes = [p]
         L.mg_batch_destroy.restype = None
+        L.mg_count_batch.argtypes = [p, p, i32, ctypes.POINTER(BatchOpts), p]
         for f in ("mg_set_allocator", "mg_graph_create", "mg_graph_info",
-                  "mg_tree_create", "mg_tree_info", "mg_count", "mg_count_noalloc", "mg_batch_create",
-                  "mg_batch_count", "mg_batch_info", "mg_model_create", "mg_model_get_weights",
+                  "mg_tree_create", "mg_tree_create_multi", "mg_tree_info", "mg_count", "mg_count_noalloc", "mg_batch_create",
+                  "mg_batch_count", "mg_batch_info", "mg_count_batch", "mg_model_create", "mg_model_get_weights",
                   "mg_model_set_weights", "mg_model_get_moments", "mg_root_features", "mg_model_predict",
                   "mg_model_train"):
             getattr(L, f).restype = ctypes.c_int
@@ -214,13 +219,22 @@ class Graph:
         L = lib()
         if torch_allocator:
             use_torch_allocator()
-        self._src = np.ascontiguousarray(src, dtype=np.int32)
-        self._dst = np.ascontiguousarray(dst, dtype=np.int32)
-        self._t = np.ascontiguousarray(t, dtype=np.int64)
+        flags = SORTED_BY_T if sorted_by_t else 0
+        if all(hasattr(x, "is_cuda") and x.is_cuda for x in (src, dst, t)):
+            # torch tensors on the GPU: handed over as device pointers
+            import torch
+            self._src = src.to(torch.int32).contiguous()
+            self._dst = dst.to(torch.int32).contiguous()
+            self._t = t.to(torch.int64).contiguous()
+            ptrs = [x.data_ptr() for x in (self._src, self._dst, self._t)]
+            flags |= DEVICE_INPUT
+        else:
+            self._src = np.ascontiguousarray(src, dtype=np.int32)
+            self._dst = np.ascontiguousarray(dst, dtype=np.int32)
+            self._t = np.ascontiguousarray(t, dtype=np.int64)
+            ptrs = [_p(x).value for x in (self._src, self._dst, self._t)]
         h = ctypes.c_void_p()
-        _check(L.mg_graph_create(_p(self._src), _p(self._dst), _p(self._t),
-                                 len(self._src), int(n_nodes),
-                                 SORTED_BY_T if sorted_by_t else 0,
+        _check(L.mg_graph_create(ptrs[0], ptrs[1], ptrs[2], len(self._src), int(n_nodes), flags,
                                  _default_stream(stream), ctypes.byref(h)))
         self._h = h
         self._L = L
@@ -246,7 +260,9 @@ class Graph:
 
 
 class Tree:
-    """The MG-Tree of a motif group for a window delta (``mg_tree_create``)."""
+    """The MG-Tree of a motif group for a window delta (``mg_tree_create``),
+    or for several windows counted in one search when ``delta`` is a list
+    (``mg_tree_create_multi``; counts then come as one row per window)."""
 
     def __init__(self, motifs, delta):
         L = lib()
@@ -255,11 +271,23 @@ class Tree:
         if uv.size == 0:
             uv = np.zeros(2, dtype=np.int32)
         h = ctypes.c_void_p()
-        _check(L.mg_tree_create(_p(uv), _p(ks), len(ks), int(delta), ctypes.byref(h)))
+        self.multi = isinstance(delta, (list, tuple, np.ndarray))
+        if self.multi:
+            ds = np.ascontiguousarray(delta, dtype=np.int64)
+            _check(L.mg_tree_create_multi(_p(uv), _p(ks), len(ks), _p(ds), len(ds),
+                                          ctypes.byref(h)))
+            self.n_deltas = len(ds)
+        else:
+            _check(L.mg_tree_create(_p(uv), _p(ks), len(ks), int(delta), ctypes.byref(h)))
+            self.n_deltas = 1
         self._h = h
         self._L = L
         self._done = _exiting
         self.n_motifs = len(ks)
+
+    def shape_counts(self, flat):
+        """Counts as mg_count returns them -> 1-D per motif, or windows x motifs."""
+        return flat.reshape(self.n_deltas, self.n_motifs) if self.multi else flat
 
     @property
     def handle(self):
@@ -327,9 +355,9 @@ def count(graph: Graph, tree: Tree, mode="comine", roots=None, blocks=0, chunk=0
     if root_cost:
         rcost = np.zeros(max(1, graph.n_edges), dtype=np.uint64)
         o.root_cost = rcost.ctypes.data
-    out = np.zeros(tree.n_motifs, dtype=np.uint64)
+    out = np.zeros(tree.n_motifs * tree.n_deltas, dtype=np.uint64)
     _check(L.mg_count(graph.handle, tree.handle, ctypes.byref(o), _p(out)))
-    res = [out]
+    res = [tree.shape_counts(out)]
     if timed:
         res.append(float(ms.value))
     if stats:
@@ -357,8 +385,9 @@ def count_noalloc(graph: Graph, tree: Tree, blocks=0, chunk=0, queues=0, stream=
     st = np.zeros(len(STAT_NAMES), dtype=np.uint64)
     if stats:
         o.stats = st.ctypes.data
-    out = np.zeros(tree.n_motifs, dtype=np.uint64)
+    out = np.zeros(tree.n_motifs * tree.n_deltas, dtype=np.uint64)
     _check(L.mg_count_noalloc(graph.handle, tree.handle, ctypes.byref(o), _p(out)))
+    out = tree.shape_counts(out)
     if stats:
         return out, {k: int(v) for k, v in zip(STAT_NAMES, st)}
     return out
@@ -436,6 +465,29 @@ def root_features(graph: Graph, tree: Tree, roots=None):
     return out[:n]
 
 
+def count_batch(graphs, trees, item_roots=0, blocks=0, stream=None, model=None):
+    """``mg_count_batch``: a batch planned, counted once and released in one
+    call.  Returns the counts per job, as ``Batch.count``."""
+    L = lib()
+    assert len(graphs) == len(trees) and len(graphs) > 0
+    o = BatchOpts()
+    L.mg_batch_opts_init(ctypes.byref(o))
+    o.item_roots, o.blocks = int(item_roots), int(blocks)
+    o.stream = _default_stream(stream)
+    if model is not None:
+        o.model = model.handle.value
+    gh = (ctypes.c_void_p * len(graphs))(*[g.handle.value for g in graphs])
+    th = (ctypes.c_void_p * len(trees))(*[t.handle.value for t in trees])
+    sizes = [t.n_motifs * t.n_deltas for t in trees]
+    out = np.zeros(sum(sizes), dtype=np.uint64)
+    _check(L.mg_count_batch(gh, th, len(graphs), ctypes.byref(o), _p(out)))
+    parts, k = [], 0
+    for n, t in zip(sizes, trees):
+        parts.append(t.shape_counts(out[k:k + n]))
+        k += n
+    return parts
+
+
 class Batch:
     """Many (graph, tree) jobs counted by one persistent launch, replayed as a
     captured HIP graph (``mg_batch_*``).  Keeps its graphs and trees alive."""
@@ -461,7 +513,7 @@ class Batch:
         self._h = h
         self._L = L
         self._done = _exiting
-        self.sizes = [t.n_motifs for t in trees]
+        self.sizes = [t.n_motifs * t.n_deltas for t in trees]
 
     def info(self) -> dict:
         bi = BatchInfo()
@@ -474,8 +526,8 @@ class Batch:
         ms = ctypes.c_float(0.0)
         _check(self._L.mg_batch_count(self._h, _p(out), ctypes.byref(ms) if timed else None))
         parts, k = [], 0
-        for n in self.sizes:
-            parts.append(out[k:k + n])
+        for n, t in zip(self.sizes, self._trees):
+            parts.append(t.shape_counts(out[k:k + n]))
             k += n
         return (parts, float(ms.value)) if timed else parts
 

@@ -9,6 +9,7 @@ namespace mg {
 constexpr int kVMax = 6;        // motif vertices
 constexpr int kKMax = 5;        // motif edges
 constexpr int kWave = 64;
+constexpr int kMaxDeltas = 8;   // windows counted in one search
 constexpr int kWavesPerBlock = 4;
 constexpr int kQueues = 8;      // root queues, one per XCD
 constexpr int kQueueStride = 16;  // u64 words between queue heads (own cache line)
@@ -46,13 +47,19 @@ enum : int { kDirOut = 0, kDirIn = 1, kDirAll = 2 };
 //     w7 = child reached when the scanned endpoint(s) are new vertices
 //   A child word is 0 when there is no such child, else
 //     internal index (bits 0-15, if internal) | (query + 1) << 16 | internal << 31.
+// Counters: n_d per distinct motif, counter q * n_d + j holding the matches
+// of motif q whose span (last time - first time) fits window j but not
+// window j - 1 (windows ascending); the count at window j is the sum of
+// slots 0..j.
 struct DevTree {
     const uint32_t *inode;
     const uint4 *grp;
-    int32_t n_q;        // distinct motifs (counter slots)
+    int32_t n_q;        // distinct motifs
     int32_t root_q;     // query id of the one-edge prefix, -1 if none
     int32_t depth;      // longest motif in edges
+    int32_t n_d;        // windows (1..kMaxDeltas), counter slots per motif
 };
+__host__ __device__ inline int32_t counter_slots(const DevTree &t) { return t.n_q * t.n_d; }
 
 // One adjacency entry: the other endpoint and the edge time, side by side so
 // that the bisection that finds a window also brings its entries into cache.
@@ -79,7 +86,8 @@ template <typename TT>
 struct KParams {
     DevGraph<TT> g;
     DevTree tree;
-    TT delta_sat;                 // delta clamped to the TT range
+    TT delta_sat;                 // the largest window, clamped to the TT range
+    TT dlo[kMaxDeltas - 1];       // the smaller windows, ascending (tree.n_d - 1 of them)
     const uint32_t *roots;        // NULL: roots are 0..n_roots-1
     uint32_t n_roots;
     uint32_t chunk;               // roots per queue grab (multiple of 64)
@@ -90,7 +98,7 @@ struct KParams {
                                   // read before every chunk claim: non-zero = claim
                                   // no more chunks
     uint32_t max_chunks;          // 0, or the launch claims at most this many chunks
-    unsigned long long *counts;   // n_q, zeroed before launch
+    unsigned long long *counts;   // counter_slots(tree), zeroed before launch
     unsigned long long *stats;    // NULL, or kStats totals (zeroed before launch)
     unsigned long long *root_cost;  // NULL, or per root edge id: 1 + window entries
                                     // examined below that root (zeroed before launch)
@@ -130,9 +138,7 @@ hipError_t launch_comine(const KParams<TT> &p, int blocks, hipStream_t stream);
 // ---- batches: many (graph, tree) jobs in one launch
 template <typename TT>
 struct BatchJob {
-    DevGraph<TT> g;
-    DevTree tree;
-    TT delta_sat;
+    KParams<TT> p;                // the job's search (roots: every edge, in order)
     uint32_t count_off;           // first counter of this job in BatchParams::counts
 };
 struct BatchItem {
@@ -145,10 +151,10 @@ struct BatchParams {
     const BatchJob<TT> *jobs;
     const BatchItem *items;
     uint32_t n_items;
-    uint32_t n_q_max;             // largest tree's counter count
+    uint32_t n_q_max;             // largest tree's counter_slots
     unsigned long long *cursor;   // item queue head, zeroed before launch
     unsigned long long *counts;   // every job's counters, zeroed before launch
-    uint32_t leaf_scan;           // as KParams::leaf_scan
+    uint32_t multi;               // 1 when some job's tree has several windows
 };
 
 // `depth` = the deepest tree of the batch.

@@ -68,12 +68,43 @@ __device__ __forceinline__ uint32_t child_word(const uint4 &a, const uint4 &b, i
     return r;
 }
 
+// The smaller window j of a multi-window tree (selects, so that the
+// parameter array is never indexed at run time: a local copy of it would go
+// to scratch memory).
+template <typename TT>
+__device__ __forceinline__ TT window_lo(const KParams<TT> &p, uint32_t j) {
+    TT r = p.dlo[0];
+#pragma unroll
+    for (int i = 1; i < kMaxDeltas - 1; ++i) r = j == (uint32_t)i ? p.dlo[i] : r;
+    return r;
+}
+
+// Window slot of a match with first time tf and last time tl: the number of
+// smaller windows its span exceeds.
+template <typename TT>
+__device__ __forceinline__ uint32_t window_slot(const KParams<TT> &p, uint32_t nd, TT tf, TT tl) {
+    uint32_t j = 0;
+#pragma unroll
+    for (int i = 0; i < kMaxDeltas - 1; ++i)
+        j += ((uint32_t)i + 1 < nd && tl > sat_add(tf, p.dlo[i])) ? 1u : 0u;
+    return j;
+}
+
+// c matches of the child in `word`, credited to window slot j of its motif
+// (nd slots per motif).  With `move`, the c matches were already credited to
+// slot j + 1 (they lie in a larger window too) and move down to slot j: slot
+// j + 1 loses them.  The counters are summed over slots modulo 2^64, so a
+// slot may hold a negative amount in between.
 __device__ __forceinline__ uint32_t credit_child(uint32_t word, uint32_t c,
-                                                unsigned long long *cnt) {
+                                                unsigned long long *cnt, uint32_t nd,
+                                                uint32_t j, bool move = false) {
     if (!c || !word) return 0;
     const uint32_t q1 = (word >> 16) & 0x7fffu;
-    if (q1) atomicAdd(&cnt[q1 - 1], (unsigned long long)c);
-    return c;
+    if (q1) {
+        atomicAdd(&cnt[(q1 - 1) * nd + j], (unsigned long long)c);
+        if (move) atomicAdd(&cnt[(q1 - 1) * nd + j + 1], 0ull - c);
+    }
+    return move ? 0u : c;
 }
 
 // Counts a leaf-only window [l0, l0 + len) of one adjacency list for one
@@ -83,12 +114,14 @@ __device__ __forceinline__ uint32_t credit_child(uint32_t word, uint32_t c,
 // child gets the rest of the window.  The list's own anchor is left out of
 // q[] (no entry equals it: lists hold no self-loops); q[0..K) are the other
 // bound vertices (-1 for none) and w[0..K) their child words, wn the
-// new-vertex child's word.  Returns the credits.
+// new-vertex child's word.  Credits go to window slot j of each motif (nd
+// slots per motif).  Returns the credits.
 template <int U, int K, typename TT, int N>
 __device__ __forceinline__ uint32_t leaf_count(const Entry<TT> *__restrict__ adj, uint32_t l0,
                                                uint32_t len, const int32_t (&q)[N],
                                                const uint32_t (&w)[N], uint32_t wn,
-                                               unsigned long long *cnt) {
+                                               unsigned long long *cnt, uint32_t nd,
+                                               uint32_t j, bool move = false) {
     static_assert(K <= N, "slots");
     uint32_t c[K];
 #pragma unroll
@@ -122,21 +155,22 @@ __device__ __forceinline__ uint32_t leaf_count(const Entry<TT> *__restrict__ adj
 #pragma unroll
     for (int s = 0; s < K; ++s) {
         hit += c[s];
-        got += credit_child(w[s], c[s], cnt);
+        got += credit_child(w[s], c[s], cnt, nd, j, move);
     }
-    return got + credit_child(wn, len - hit, cnt);
+    return got + credit_child(wn, len - hit, cnt, nd, j, move);
 }
 
 
 // Counts the leaf-only window [l0, l0 + len) of group g for the partial match
 // with bound vertices ph[] with the whole wave, 64 entries per pass: one ballot per bound
 // vertex counts the entries that hit it, and the new-vertex child gets the
-// rest.  All arguments are wave-uniform.  Returns the credits on lane 0
-// (0 on the other lanes).
+// rest.  All arguments are wave-uniform.  Credits go to window slot j.
+// Returns the credits on lane 0 (0 on the other lanes).
 template <typename TT, int SA>
 __device__ __forceinline__ uint32_t leaf_scan_wave(const KParams<TT> &p, const int32_t (&ph)[SA],
                                                    uint32_t g, uint32_t l0, uint32_t len,
-                                                   const int lane, unsigned long long *cnt) {
+                                                   const int lane, unsigned long long *cnt,
+                                                   uint32_t nd, uint32_t j, bool move = false) {
     const uint4 ga = p.tree.grp[2 * g], gb = p.tree.grp[2 * g + 1];
     const uint32_t nvp = (ga.x >> 8) & 15;
     const Entry<TT> *__restrict__ e =
@@ -169,9 +203,9 @@ __device__ __forceinline__ uint32_t leaf_scan_wave(const KParams<TT> &p, const i
 #pragma unroll
     for (int s = 0; s < SA; ++s) {
         hit += c[s];
-        got += credit_child(words[s], c[s], cnt);
+        got += credit_child(words[s], c[s], cnt, nd, j, move);
     }
-    return got + credit_child(gb.w, len - hit, cnt);
+    return got + credit_child(gb.w, len - hit, cnt, nd, j, move);
 }
 
 // Partial matches with L motif edges matched.  Level 1 is the root batch:
@@ -259,7 +293,8 @@ struct Stats {
     uint64_t v[kStats];
 };
 
-// MODE: 0 plain search, 1 with search statistics, 2 with the per-root cost log
+// MODE: 0 plain search (trees with one window), 1 with search statistics, 2
+// with the per-root cost log, 3 plain search of a tree with several windows
 // At level 1 with nparts > 1 (one buffered root), only part `part` of the
 // root's candidates is expanded: [T * part / nparts, T * (part + 1) / nparts)
 // of its T candidates in window order, so that the parts of one root
@@ -286,6 +321,8 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
     const uint32_t *__restrict__ inode = p.tree.inode;
     const uint4 *__restrict__ grp = p.tree.grp;
     const uint64_t le_mask = (lane == 63) ? ~0ull : ((2ull << lane) - 1);
+    // windows counted at once (MODE 0 serves trees with one window only)
+    const uint32_t nd = MODE == 0 ? 1u : (uint32_t)p.tree.n_d;
 
 
     // child groups per buffered partial match -> inclusive prefix (at the
@@ -461,12 +498,29 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                     const Entry<TT> *adj = (hdr & 15) == kDirOut ? p.g.out_adj : p.g.in_adj;
                     // loads per step (measured: 8 for trees up to depth 3, 4 deeper)
                     constexpr int kLU = D <= 3 ? 8 : 4;
-                    uint32_t c = 0;
-                    if constexpr (NQ >= 1) if (nqm == 1) c = leaf_count<kLU, 1>(adj, l0, len, q, w, gb.w, cnt);
-                    if constexpr (NQ >= 2) if (nqm == 2) c = leaf_count<kLU, 2>(adj, l0, len, q, w, gb.w, cnt);
-                    if constexpr (NQ >= 3) if (nqm == 3) c = leaf_count<kLU, 3>(adj, l0, len, q, w, gb.w, cnt);
-                    if constexpr (NQ >= 4) if (nqm == 4) c = leaf_count<kLU, 4>(adj, l0, len, q, w, gb.w, cnt);
-                    if constexpr (NQ >= 5) if (nqm == 5) c = leaf_count<kLU, 5>(adj, l0, len, q, w, gb.w, cnt);
+                    auto count = [&](uint32_t n, uint32_t j, bool move) -> uint32_t {
+                        uint32_t c = 0;
+                        if constexpr (NQ >= 1) if (nqm == 1) c = leaf_count<kLU, 1>(adj, l0, n, q, w, gb.w, cnt, nd, j, move);
+                        if constexpr (NQ >= 2) if (nqm == 2) c = leaf_count<kLU, 2>(adj, l0, n, q, w, gb.w, cnt, nd, j, move);
+                        if constexpr (NQ >= 3) if (nqm == 3) c = leaf_count<kLU, 3>(adj, l0, n, q, w, gb.w, cnt, nd, j, move);
+                        if constexpr (NQ >= 4) if (nqm == 4) c = leaf_count<kLU, 4>(adj, l0, n, q, w, gb.w, cnt, nd, j, move);
+                        if constexpr (NQ >= 5) if (nqm == 5) c = leaf_count<kLU, 5>(adj, l0, n, q, w, gb.w, cnt, nd, j, move);
+                        return c;
+                    };
+                    // the whole window counts at the largest window
+                    const uint32_t c = count(len, nd - 1, false);
+                    if constexpr (MODE != 0) {
+                        // each smaller window is a prefix of this one: its
+                        // matches move down one slot (usually it is empty)
+                        const TT *ta = times_of(adj);
+                        const TT tf = tfirst_of(x);
+                        uint32_t e = l0 + len;
+                        for (uint32_t j = nd - 1; j-- > 0;) {
+                            e = gallop_greater(ta, 1, l0, e, sat_add(tf, window_lo(p, j)));
+                            if (e == l0) break;
+                            count(e - l0, j, true);
+                        }
+                    }
                     if constexpr (STATS) st.v[kStatCredit] += c;
                 }
                 for (uint64_t cm = __ballot(coop && own); cm; cm &= cm - 1) {
@@ -475,9 +529,22 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                     int32_t wph[SA];
 #pragma unroll
                     for (int t = 0; t < SA; ++t) wph[t] = (int32_t)uniform((uint32_t)vtx(t, wx));
-                    const uint32_t c = leaf_scan_wave<TT, SA>(
-                        p, wph, __builtin_amdgcn_readlane(g, src), __builtin_amdgcn_readlane(l0, src),
-                        __builtin_amdgcn_readlane(len, src), lane, cnt);
+                    const uint32_t wg = __builtin_amdgcn_readlane(g, src);
+                    const uint32_t wl0 = __builtin_amdgcn_readlane(l0, src);
+                    const uint32_t wlen = __builtin_amdgcn_readlane(len, src);
+                    const uint32_t c = leaf_scan_wave<TT, SA>(p, wph, wg, wl0, wlen, lane, cnt, nd,
+                                                              nd - 1);
+                    if constexpr (MODE != 0) {
+                        const TT *ta = times_of((grp[2 * wg].x & 15) == kDirOut ? p.g.out_adj
+                                                                                : p.g.in_adj);
+                        const TT tf = tfirst_of(wx);
+                        uint32_t e = wl0 + wlen;
+                        for (uint32_t j = nd - 1; j-- > 0;) {
+                            e = uniform(gallop_greater(ta, 1, wl0, e, sat_add(tf, window_lo(p, j))));
+                            if (e == wl0) break;
+                            leaf_scan_wave<TT, SA>(p, wph, wg, wl0, e - wl0, lane, cnt, nd, j, true);
+                        }
+                    }
                     if constexpr (STATS) st.v[kStatCredit] += c;
                 }
                 // compact the other non-empty windows into lanes 0..nw-1; their
@@ -568,11 +635,15 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                     cw = hit ? 0u : gb.w;
                     nv0 = cs;
                     nv1 = cd;
+                    tn = p.g.gt[ei];
                 }
             }
             if (cw) {
                 const uint32_t q1 = (cw >> 16) & 0x7fffu;
-                if (q1) atomicAdd(&cnt[q1 - 1], 1ull);
+                if (q1) {
+                    const uint32_t j = nd > 1 ? window_slot(p, nd, tfirst_of(ox), tn) : 0u;
+                    atomicAdd(&cnt[(q1 - 1) * nd + j], 1ull);
+                }
                 if constexpr (STATS) st.v[kStatCredit] += 1;
             }
             if constexpr (L + 1 < D) {
@@ -581,7 +652,7 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                 const bool push = (cw >> 31) != 0;
                 const uint64_t pm = __ballot(push);
                 if (push) {
-                    const TT tnew = dir == kDirAll ? p.g.gt[ei] : tn;
+                    const TT tnew = tn;
                     const uint32_t slot = nB + mbcnt(pm);
 #pragma unroll
                     for (int s = 2; s < SB; ++s) {
@@ -625,7 +696,7 @@ __device__ __forceinline__ void process_root_part(const KParams<TT> &p,
     const int32_t s = p.g.gsrc[r], d = p.g.gdst[r];
     if (s == d) return;
     if (part == 0) {
-        if (p.tree.root_q >= 0 && lane == 0) atomicAdd(&cnt[p.tree.root_q], 1ull);
+        if (p.tree.root_q >= 0 && lane == 0) atomicAdd(&cnt[p.tree.root_q * p.tree.n_d], 1ull);
         if constexpr (STATS) st.v[kStatRoots] += lane == 0 ? 1 : 0;
         if constexpr (LOG) {
             if (lane == 0) atomicAdd(&p.root_cost[r], 1ull);
@@ -668,7 +739,7 @@ __device__ __forceinline__ void process_roots(const KParams<TT> &p,
         }
         const uint64_t m = __ballot(ok);
         if (p.tree.root_q >= 0 && lane == 0 && m)
-            atomicAdd(&cnt[p.tree.root_q], (unsigned long long)__popcll(m));
+            atomicAdd(&cnt[p.tree.root_q * p.tree.n_d], (unsigned long long)__popcll(m));
         if constexpr (STATS) st.v[kStatRoots] += ok ? 1 : 0;
         if constexpr (LOG) {
             if (ok) atomicAdd(&p.root_cost[r], 1ull);
@@ -693,25 +764,27 @@ __device__ __forceinline__ void process_roots(const KParams<TT> &p,
     }
 }
 
-// Up to depth 3 the search fits 8 waves per SIMD (at most 64 VGPRs and 96
-// SGPRs) without spilling in its timed form; the compiler is asked for that.
-// Deeper trees keep the compiler's own allocation.
-template <int D>
-constexpr int min_waves_per_eu() { return D <= 3 ? 8 : 1; }
+// Up to depth 3 the plain search (MODE 0) fits 8 waves per SIMD (at most 64
+// VGPRs and 96 SGPRs) without spilling in its loops; the compiler is asked
+// for that.  Deeper trees and the other modes keep the compiler's own
+// allocation.
+template <int D, int MODE>
+constexpr int min_waves_per_eu() { return D <= 3 && MODE == 0 ? 8 : 1; }
 
 template <typename TT, int D, int MODE>
 __global__ void __launch_bounds__(kWave * kWavesPerBlock)
-__attribute__((amdgpu_waves_per_eu(min_waves_per_eu<D>(), 8)))
+__attribute__((amdgpu_waves_per_eu(min_waves_per_eu<D, MODE>(), 8)))
 comine_kernel(const KParams<TT> p) {
     constexpr bool STATS = MODE == 1, LOG = MODE == 2;
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned long long *cnt = reinterpret_cast<unsigned long long *>(smem);
-    const size_t cnt_bytes = ((size_t)p.tree.n_q * 8 + 15) & ~(size_t)15;
+    const int32_t n_slots = counter_slots(p.tree);
+    const size_t cnt_bytes = ((size_t)n_slots * 8 + 15) & ~(size_t)15;
     const int lane = (int)(threadIdx.x & (kWave - 1));
     const int wave = (int)(threadIdx.x / kWave);
     WaveLds<TT, D, LOG> &W = reinterpret_cast<WaveLds<TT, D, LOG> *>(smem + cnt_bytes)[wave];
 
-    for (int i = (int)threadIdx.x; i < p.tree.n_q; i += (int)blockDim.x) cnt[i] = 0;
+    for (int i = (int)threadIdx.x; i < n_slots; i += (int)blockDim.x) cnt[i] = 0;
     W.flag[lane] = 0;
     __syncthreads();
     Stats st;
@@ -749,13 +822,24 @@ comine_kernel(const KParams<TT> p) {
         for (;;) {
             unsigned long long got = 0;
             if (lane == 0) {
-                bool go = true;
-                if (p.stop) go = __hip_atomic_load(p.stop, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_SYSTEM) == 0;
-                if (go && p.max_chunks)
-                    go = atomicAdd(&p.queues[kBudgetSlot * kQueueStride], 1ull) < p.max_chunks;
-                got = go ? atomicAdd(&p.queues[q * kQueueStride], (unsigned long long)p.chunk)
-                         : ~0ull;
+                unsigned long long *head = &p.queues[q * kQueueStride];
+                if (p.stop && __hip_atomic_load(p.stop, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_SYSTEM) != 0) {
+                    got = ~0ull;
+                } else if (p.max_chunks) {
+                    // the budget is spent only on a queue that still has roots,
+                    // so a call makes progress while any root is left: a
+                    // budget holder's claim fails only when another holder
+                    // took the last chunk
+                    const unsigned long long h =
+                        __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (h >= (unsigned long long)(qend - qbeg)) got = h;
+                    else if (atomicAdd(&p.queues[kBudgetSlot * kQueueStride], 1ull) >= p.max_chunks)
+                        got = ~0ull;
+                    else got = atomicAdd(head, (unsigned long long)p.chunk);
+                } else {
+                    got = atomicAdd(head, (unsigned long long)p.chunk);
+                }
             }
             got = lane0_u64(got);
             if (got == ~0ull) { stopped = true; break; }
@@ -772,14 +856,14 @@ comine_kernel(const KParams<TT> p) {
             if (st.v[i]) atomicAdd(&p.stats[i], (unsigned long long)st.v[i]);
     }
     __syncthreads();
-    for (int i = (int)threadIdx.x; i < p.tree.n_q; i += (int)blockDim.x)
+    for (int i = (int)threadIdx.x; i < n_slots; i += (int)blockDim.x)
         if (cnt[i]) atomicAdd(&p.counts[i], cnt[i]);
 }
 
 // Many (graph, tree) jobs in one persistent launch.  Waves claim work items
 // (root ranges of one job) from one queue; each wave keeps its own LDS
 // counters, sized for the largest tree, and flushes them after every item.
-template <typename TT, int D>
+template <typename TT, int D, int MODE>
 __global__ void __launch_bounds__(kWave * kWavesPerBlock)
 batch_kernel(const BatchParams<TT> bp) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -798,21 +882,27 @@ batch_kernel(const BatchParams<TT> bp) {
         if (it >= bp.n_items) break;
         const BatchItem item = bp.items[uniform((uint32_t)it)];
         const BatchJob<TT> &job = bp.jobs[uniform(item.job)];
-        KParams<TT> p{};
-        p.g = job.g;
-        p.tree = job.tree;
-        p.delta_sat = job.delta_sat;
-        p.roots = nullptr;
-        p.leaf_scan = bp.leaf_scan;
-        const uint32_t nq = (uint32_t)p.tree.n_q;
+        // the plain search keeps its own copy of the job's parameters (in
+        // registers); the multi-window one reads them in place, since its
+        // window selection would otherwise put a copy in scratch memory
+        auto search = [&](const KParams<TT> &p) {
+            const uint32_t ip = uniform(item.part);
+            if (ip & kItemSplit)
+                process_root_part<TT, D, MODE>(p, W, cnt, lane, uniform(item.begin),
+                                               (ip >> 15) & 0x7fffu, ip & 0x7fffu, st);
+            else
+                process_roots<TT, D, MODE>(p, W, cnt, lane, uniform(item.begin), uniform(item.end),
+                                           st);
+        };
+        const uint32_t nq = (uint32_t)counter_slots(job.p.tree);
         for (uint32_t i = (uint32_t)lane; i < nq; i += kWave) cnt[i] = 0;
         wave_sync();
-        const uint32_t ip = uniform(item.part);
-        if (ip & kItemSplit)
-            process_root_part<TT, D, 0>(p, W, cnt, lane, uniform(item.begin), (ip >> 15) & 0x7fffu,
-                                        ip & 0x7fffu, st);
-        else
-            process_roots<TT, D, 0>(p, W, cnt, lane, uniform(item.begin), uniform(item.end), st);
+        if constexpr (MODE == 0) {
+            const KParams<TT> p = job.p;
+            search(p);
+        } else {
+            search(job.p);
+        }
         wave_sync();
         for (uint32_t i = (uint32_t)lane; i < nq; i += kWave)
             if (cnt[i]) atomicAdd(&bp.counts[job.count_off + i], cnt[i]);
@@ -833,7 +923,7 @@ size_t smem_bytes(int n_q) {
 
 template <typename TT, int D, int MODE>
 hipError_t launch_ds(const KParams<TT> &p, int blocks, hipStream_t stream) {
-    const size_t sm = smem_bytes<TT, D, MODE>(p.tree.n_q);
+    const size_t sm = smem_bytes<TT, D, MODE>(counter_slots(p.tree));
     auto kern = comine_kernel<TT, D, MODE>;
     if (sm > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)kern,
@@ -858,14 +948,15 @@ template <typename TT, int D>
 hipError_t launch_d(const KParams<TT> &p, int blocks, hipStream_t stream) {
     if (p.stats) return launch_ds<TT, D, 1>(p, blocks, stream);
     if (p.root_cost) return launch_ds<TT, D, 2>(p, blocks, stream);
+    if (p.tree.n_d > 1) return launch_ds<TT, D, 3>(p, blocks, stream);
     return launch_ds<TT, D, 0>(p, blocks, stream);
 }
 
-template <typename TT, int D>
+template <typename TT, int D, int MODE>
 hipError_t launch_batch_d(const BatchParams<TT> &bp, int blocks, hipStream_t stream) {
     const size_t sm = (size_t)kWavesPerBlock *
                       ((((size_t)bp.n_q_max * 8 + 15) & ~(size_t)15) + sizeof(WaveLds<TT, D, false>));
-    auto kern = batch_kernel<TT, D>;
+    auto kern = batch_kernel<TT, D, MODE>;
     if (sm > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)kern,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
@@ -889,12 +980,22 @@ hipError_t launch_batch_d(const BatchParams<TT> &bp, int blocks, hipStream_t str
 
 template <typename TT>
 hipError_t launch_batch(const BatchParams<TT> &bp, int depth, int blocks, hipStream_t stream) {
+    if (bp.multi) {
+        switch (depth) {
+            case 1: return launch_batch_d<TT, 1, 3>(bp, blocks, stream);
+            case 2: return launch_batch_d<TT, 2, 3>(bp, blocks, stream);
+            case 3: return launch_batch_d<TT, 3, 3>(bp, blocks, stream);
+            case 4: return launch_batch_d<TT, 4, 3>(bp, blocks, stream);
+            case 5: return launch_batch_d<TT, 5, 3>(bp, blocks, stream);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (depth) {
-        case 1: return launch_batch_d<TT, 1>(bp, blocks, stream);
-        case 2: return launch_batch_d<TT, 2>(bp, blocks, stream);
-        case 3: return launch_batch_d<TT, 3>(bp, blocks, stream);
-        case 4: return launch_batch_d<TT, 4>(bp, blocks, stream);
-        case 5: return launch_batch_d<TT, 5>(bp, blocks, stream);
+        case 1: return launch_batch_d<TT, 1, 0>(bp, blocks, stream);
+        case 2: return launch_batch_d<TT, 2, 0>(bp, blocks, stream);
+        case 3: return launch_batch_d<TT, 3, 0>(bp, blocks, stream);
+        case 4: return launch_batch_d<TT, 4, 0>(bp, blocks, stream);
+        case 5: return launch_batch_d<TT, 5, 0>(bp, blocks, stream);
         default: return hipErrorInvalidValue;
     }
 }

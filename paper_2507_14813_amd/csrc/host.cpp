@@ -4,6 +4,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -29,6 +30,7 @@ constexpr uint32_t kRootParts = 16;
 constexpr size_t kQueueBytes = sizeof(unsigned long long) * mg::kQueueWords;
 static_assert(MG_CURSOR_QUEUES == mg::kQueues, "cursor layout");
 static_assert(MG_MAX_QUERIES == mg::kMaxQueries, "query limit");
+static_assert(MG_MAX_DELTAS == mg::kMaxDeltas, "window limit");
 static_assert(MG_NOALLOC_SCRATCH_BYTES == 8 * mg::kStaticWords, "static scratch size");
 
 namespace {
@@ -188,7 +190,9 @@ using Motif = std::vector<std::pair<int, int>>;
 
 struct mg_tree {
     int32_t n_motifs = 0;
-    int64_t delta = 0;
+    int64_t delta = 0;                  // the largest window
+    std::vector<int64_t> deltas;        // distinct windows, ascending
+    std::vector<int32_t> delta_slot;    // caller's window i -> index in deltas
     std::vector<int32_t> motif_q;       // caller motif -> distinct id
     std::vector<Motif> distinct;
     std::vector<TrieNode> nodes;        // node 0 = prefix ((0,1))
@@ -348,14 +352,22 @@ int build_tree(mg_tree *tr) {
     in.root_edges = tr->nodes[r].depth;
     in.similarity = total_edges ? 1.0 - (double)N / (double)total_edges : 0.0;
     in.delta = tr->delta;
+    in.n_deltas = (int32_t)tr->delta_slot.size();
     return MG_OK;
 }
 
-int make_tree(const std::vector<Motif> &canon, int64_t delta, mg_tree **out) {
+int make_tree(const std::vector<Motif> &canon, const std::vector<int64_t> &windows,
+              mg_tree **out) {
     std::unique_ptr<mg_tree> tr(new (std::nothrow) mg_tree);
     if (!tr) return fail(MG_ENOMEM, "out of host memory");
     tr->n_motifs = (int32_t)canon.size();
-    tr->delta = delta;
+    tr->deltas = windows;
+    std::sort(tr->deltas.begin(), tr->deltas.end());
+    tr->deltas.erase(std::unique(tr->deltas.begin(), tr->deltas.end()), tr->deltas.end());
+    for (int64_t w : windows)
+        tr->delta_slot.push_back(
+            (int32_t)(std::lower_bound(tr->deltas.begin(), tr->deltas.end(), w) - tr->deltas.begin()));
+    tr->delta = tr->deltas.back();
     std::map<Motif, int> ids;
     for (const Motif &m : canon) {
         auto it = ids.find(m);
@@ -372,11 +384,30 @@ int make_tree(const std::vector<Motif> &canon, int64_t delta, mg_tree **out) {
     if ((int)tr->distinct.size() > MG_MAX_QUERIES)
         return fail(MG_EUNSUPPORTED, "%d distinct motifs (limit %d)", (int)tr->distinct.size(),
                     MG_MAX_QUERIES);
+    if (tr->distinct.size() * tr->deltas.size() > (size_t)MG_MAX_QUERIES)
+        return fail(MG_EUNSUPPORTED, "%d distinct motifs x %d windows exceed %d counters",
+                    (int)tr->distinct.size(), (int)tr->deltas.size(), MG_MAX_QUERIES);
     int rc = build_tree(tr.get());
     if (rc) return rc;
     *out = tr.release();
     return MG_OK;
 }
+
+// Caller-visible counts of one tree from its counters (n_d slots per
+// distinct motif; slot j holds the matches whose span fits window j but not
+// window j - 1): out[i * n_motifs + m] for the caller's window i and motif m.
+void map_counts(const mg_tree *tr, const uint64_t *slots, uint64_t *out) {
+    const size_t nd = tr->deltas.size();
+    for (size_t i = 0; i < tr->delta_slot.size(); ++i)
+        for (int32_t m = 0; m < tr->n_motifs; ++m) {
+            const uint64_t *c = slots + (size_t)tr->motif_q[m] * nd;
+            uint64_t sum = 0;
+            for (int32_t j = 0; j <= tr->delta_slot[i]; ++j) sum += c[j];
+            out[i * (size_t)tr->n_motifs + m] = sum;
+        }
+}
+
+size_t n_slots(const mg_tree *tr) { return tr->distinct.size() * tr->deltas.size(); }
 
 int upload_tree(mg_tree *tr, int device, hipStream_t st) {
     if (tr->device == device && tr->d_node.ptr) return MG_OK;
@@ -414,6 +445,7 @@ void fill_params(mg::KParams<TT> &p, const mg_graph *g, const mg_tree *tr, const
     p.g = dev_graph<TT>(g);
     p.tree = dev_tree(tr);
     p.delta_sat = delta_sat<TT>(tr->delta);
+    for (size_t i = 0; i + 1 < tr->deltas.size(); ++i) p.dlo[i] = delta_sat<TT>(tr->deltas[i]);
     p.roots = nullptr;
     p.n_roots = (uint32_t)g->E;
     p.chunk = (uint32_t)(o.chunk > 0 ? o.chunk : 64);
@@ -448,7 +480,7 @@ int launch_tree(const mg_graph *g, mg_tree *tr, const uint32_t *d_roots, uint32_
         HIP_TRY(hipMemsetAsync(d_queues, 0, kQueueBytes, st));
     }
     if (d_stats) HIP_TRY(hipMemsetAsync(d_stats, 0, sizeof(unsigned long long) * mg::kStats, st));
-    HIP_TRY(hipMemsetAsync(d_counts, 0, sizeof(unsigned long long) * p.tree.n_q, st));
+    HIP_TRY(hipMemsetAsync(d_counts, 0, sizeof(unsigned long long) * mg::counter_slots(p.tree), st));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (ms) {
         HIP_TRY(hipEventCreate(&e0));
@@ -526,6 +558,7 @@ mg::DevTree dev_tree(const mg_tree *tr) {
     t.n_q = (int32_t)tr->distinct.size();
     t.root_q = tr->root_q;
     t.depth = tr->depth;
+    t.n_d = (int32_t)tr->deltas.size();
     return t;
 }
 
@@ -600,6 +633,7 @@ struct mg_batch {
     mg_batch_opts opts{};
     int32_t item_roots = 0;
     float tuned_ms = 0.f;
+    float predict_ms = 0.f;       // features + MLP + ordering at plan creation
     bool learned = false;
     std::vector<mg::BatchItem> items;
     DevBuf d_jobs, d_items, d_work;   // d_work: cursor (16 B) + counters
@@ -623,19 +657,12 @@ namespace {
 template <typename TT>
 int upload_jobs(mg_batch *b, hipStream_t st) {
     std::vector<mg::BatchJob<TT>> jobs(b->graphs.size());
+    mg_count_opts o;
+    mg_count_opts_init(&o);
     for (size_t j = 0; j < jobs.size(); ++j) {
-        const mg_graph *g = b->graphs[j];
-        mg_tree *tr = b->trees[j];
         mg::BatchJob<TT> &J = jobs[j];
         std::memset(&J, 0, sizeof J);
-        J.g = dev_graph<TT>(g);
-        J.tree.inode = (const uint32_t *)tr->d_node.ptr;
-        J.tree.grp = (const uint4 *)tr->d_grp.ptr;
-        J.tree.n_q = (int32_t)tr->distinct.size();
-        J.tree.root_q = tr->root_q;
-        J.tree.depth = tr->depth;
-        J.delta_sat = sizeof(TT) == 4 ? (TT)std::min<uint64_t>((uint64_t)tr->delta, 0xffffffffull)
-                                      : (TT)(uint64_t)tr->delta;
+        fill_params<TT>(J.p, b->graphs[j], b->trees[j], o, nullptr, nullptr, nullptr, nullptr);
         J.count_off = b->count_off[j];
     }
     int rc = dev_alloc(b->d_jobs, sizeof(mg::BatchJob<TT>) * jobs.size(), (void *)st);
@@ -683,6 +710,7 @@ int predict_job_segments(const mg_graph *g, mg_tree *tr, const mg_model *m, floa
 }
 
 int learned_items(mg_batch *b, const mg_model *m, hipStream_t st) {
+    const auto t0 = std::chrono::steady_clock::now();
     struct Seg { float cost; uint32_t job, first, end; };
     std::vector<Seg> segs;
     double total = 0.0;
@@ -764,6 +792,8 @@ int learned_items(mg_batch *b, const mg_model *m, hipStream_t st) {
                                sizeof(mg::BatchItem) * b->items.size(), hipMemcpyHostToDevice, st));
     b->item_roots = mg::kSeg;
     b->learned = true;
+    HIP_TRY(hipStreamSynchronize(st));
+    b->predict_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return MG_OK;
 }
 
@@ -777,7 +807,8 @@ int enqueue_step(mg_batch *b, hipStream_t st) {
     bp.n_q_max = b->n_q_max;
     bp.cursor = (unsigned long long *)b->d_work.ptr;
     bp.counts = (unsigned long long *)((char *)b->d_work.ptr + 16);
-    bp.leaf_scan = mg::kLeafScanDefault;
+    bp.multi = 0;
+    for (const mg_tree *tr : b->trees) bp.multi |= tr->deltas.size() > 1 ? 1u : 0u;
     hipError_t e = mg::launch_fill_u64(bp.cursor, 2 + b->total_q, 0ull, st);
     if (e != hipSuccess) return fail(MG_EDEVICE, "fill launch failed: %s", hipGetErrorString(e));
     if (bp.n_items) {
@@ -1041,10 +1072,10 @@ int mg_batch_create(const mg_graph *const *graphs, const mg_tree *const *trees, 
             b->graphs.push_back(graphs[j]);
             b->trees.push_back(tr);
             b->count_off.push_back(b->total_q);
-            b->total_q += (uint32_t)tr->distinct.size();
-            b->total_motifs += tr->n_motifs;
+            b->total_q += (uint32_t)n_slots(tr);
+            b->total_motifs += tr->n_motifs * (int32_t)tr->delta_slot.size();
             b->total_roots += graphs[j]->E;
-            b->n_q_max = std::max<uint32_t>(b->n_q_max, (uint32_t)tr->distinct.size());
+            b->n_q_max = std::max<uint32_t>(b->n_q_max, (uint32_t)n_slots(tr));
             b->depth = std::max(b->depth, tr->depth);
         }
         b->time_bytes = graphs[0]->time_bytes;
@@ -1111,11 +1142,11 @@ int mg_batch_count(mg_batch *b, uint64_t *counts, float *elapsed_ms) {
         }
         rc = run_step(b, st, elapsed_ms);
         if (rc) return rc;
-        int32_t k = 0;
+        size_t k = 0;
         for (size_t j = 0; j < b->trees.size(); ++j) {
             const mg_tree *tr = b->trees[j];
-            for (int32_t i = 0; i < tr->n_motifs; ++i)
-                counts[k++] = b->h_counts[b->count_off[j] + tr->motif_q[i]];
+            map_counts(tr, b->h_counts + b->count_off[j], counts + k);
+            k += (size_t)tr->n_motifs * tr->delta_slot.size();
         }
         return MG_OK;
     } catch (...) {
@@ -1135,10 +1166,27 @@ int mg_batch_info(const mg_batch *b, mg_batch_info_t *out) {
     out->depth = b->depth;
     out->tuned_ms = b->tuned_ms;
     out->learned = b->learned ? 1 : 0;
+    out->predict_ms = b->predict_ms;
     return MG_OK;
 }
 
 void mg_batch_destroy(mg_batch *b) { delete b; }
+
+int mg_count_batch(const mg_graph *const *graphs, const mg_tree *const *trees, int32_t n,
+                   const mg_batch_opts *opts, uint64_t *counts) {
+    if (!counts) return fail(MG_EINVAL, "NULL counts");
+    mg_batch_opts o;
+    mg_batch_opts_init(&o);
+    if (opts) o = *opts;
+    o.use_graph = 0;
+    if (o.item_roots == 0) o.item_roots = 64;
+    mg_batch *b = nullptr;
+    int rc = mg_batch_create(graphs, trees, n, &o, &b);
+    if (rc) return rc;
+    rc = mg_batch_count(b, counts, nullptr);
+    mg_batch_destroy(b);
+    return rc;
+}
 
 int mg_graph_create(const int32_t *src, const int32_t *dst, const int64_t *t, int64_t n_edges,
                     int32_t n_nodes, uint32_t flags, void *stream, mg_graph **out) {
@@ -1149,6 +1197,23 @@ int mg_graph_create(const int32_t *src, const int32_t *dst, const int64_t *t, in
         if (n_edges >= (int64_t)1 << 31)
             return fail(MG_EUNSUPPORTED, "n_edges %lld >= 2^31", (long long)n_edges);
         if (n_nodes >= INT32_MAX) return fail(MG_EUNSUPPORTED, "n_nodes too large");
+        if (flags & ~(MG_SORTED_BY_T | MG_DEVICE_INPUT)) return fail(MG_EINVAL, "unknown flags");
+        std::vector<int32_t> hs, hd;
+        std::vector<int64_t> ht;
+        if ((flags & MG_DEVICE_INPUT) && n_edges > 0) {
+            // device arrays: brought to the host, where the adjacency is built
+            hs.resize(n_edges);
+            hd.resize(n_edges);
+            ht.resize(n_edges);
+            hipStream_t st = (hipStream_t)stream;
+            HIP_TRY(hipMemcpyAsync(hs.data(), src, 4 * (size_t)n_edges, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipMemcpyAsync(hd.data(), dst, 4 * (size_t)n_edges, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipMemcpyAsync(ht.data(), t, 8 * (size_t)n_edges, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            src = hs.data();
+            dst = hd.data();
+            t = ht.data();
+        }
         for (int64_t i = 0; i < n_edges; ++i)
             if (src[i] < 0 || src[i] >= n_nodes || dst[i] < 0 || dst[i] >= n_nodes)
                 return fail(MG_EINVAL, "edge %lld has a vertex outside [0, %d)", (long long)i,
@@ -1213,10 +1278,19 @@ void mg_graph_destroy(mg_graph *g) { delete g; }
 
 int mg_tree_create(const int32_t *motif_uv, const int32_t *motif_k, int32_t n_motifs,
                    int64_t delta, mg_tree **out) {
+    return mg_tree_create_multi(motif_uv, motif_k, n_motifs, &delta, 1, out);
+}
+
+int mg_tree_create_multi(const int32_t *motif_uv, const int32_t *motif_k, int32_t n_motifs,
+                         const int64_t *deltas, int32_t n_deltas, mg_tree **out) {
     try {
         if (!out) return fail(MG_EINVAL, "out is NULL");
         if (n_motifs < 1 || !motif_uv || !motif_k) return fail(MG_EINVAL, "no motifs");
-        if (delta < 0) return fail(MG_EINVAL, "delta < 0");
+        if (!deltas || n_deltas < 1) return fail(MG_EINVAL, "no window");
+        if (n_deltas > MG_MAX_DELTAS)
+            return fail(MG_EUNSUPPORTED, "%d windows (limit %d)", n_deltas, MG_MAX_DELTAS);
+        for (int32_t i = 0; i < n_deltas; ++i)
+            if (deltas[i] < 0) return fail(MG_EINVAL, "delta < 0");
         std::vector<Motif> canon(n_motifs);
         int64_t off = 0;
         for (int32_t i = 0; i < n_motifs; ++i) {
@@ -1228,7 +1302,7 @@ int mg_tree_create(const int32_t *motif_uv, const int32_t *motif_k, int32_t n_mo
             if (rc) return rc;
             off += k;
         }
-        return make_tree(canon, delta, out);
+        return make_tree(canon, std::vector<int64_t>(deltas, deltas + n_deltas), out);
     } catch (const std::bad_alloc &) {
         return fail(MG_ENOMEM, "out of host memory");
     } catch (...) {
@@ -1261,9 +1335,9 @@ int mg_count_noalloc(const mg_graph *g, const mg_tree *tr, const mg_count_opts *
             return fail(MG_EINVAL, "queues must be in [0, %d]", mg::kQueues);
         if (o.max_chunks < 0 || o.max_chunks > 0xffffffffll)
             return fail(MG_EINVAL, "max_chunks must be in [0, 2^32)");
-        const size_t nq = tr->distinct.size();
+        const size_t nq = n_slots(tr);
         if (nq > (size_t)mg::kMaxQueries)
-            return fail(MG_EUNSUPPORTED, "%zu distinct motifs; the static counters hold %d", nq,
+            return fail(MG_EUNSUPPORTED, "%zu counters; the static array holds %d", nq,
                         mg::kMaxQueries);
         int dev = 0;
         HIP_TRY(hipGetDevice(&dev));
@@ -1301,7 +1375,7 @@ int mg_count_noalloc(const mg_graph *g, const mg_tree *tr, const mg_count_opts *
         if (nq) HIP_TRY(hipMemcpyAsync(h, d_counts, 8 * nq, hipMemcpyDeviceToHost, st));
         if (d_stats) HIP_TRY(hipMemcpyAsync(hs, d_stats, sizeof hs, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
-        for (int32_t i = 0; i < tr->n_motifs; ++i) counts[i] = h[tr->motif_q[i]];
+        map_counts(tr, h, counts);
         if (o.stats) std::copy(hs, hs + mg::kStats, o.stats);
         return MG_OK;
     } catch (...) {
@@ -1395,7 +1469,7 @@ int mg_count(const mg_graph *g, const mg_tree *tr_c, const mg_count_opts *opts,
             if (tr->singles.empty()) {
                 for (const Motif &m : tr->distinct) {
                     mg_tree *one = nullptr;
-                    int rc = make_tree({m}, tr->delta, &one);
+                    int rc = make_tree({m}, tr->deltas, &one);
                     if (rc) return rc;
                     tr->singles.emplace_back(one);
                 }
@@ -1403,7 +1477,7 @@ int mg_count(const mg_graph *g, const mg_tree *tr_c, const mg_count_opts *opts,
             for (auto &u : tr->singles) runs.push_back(u.get());
         }
         size_t maxq = 1;
-        for (mg_tree *t : runs) maxq = std::max(maxq, t->distinct.size());
+        for (mg_tree *t : runs) maxq = std::max(maxq, n_slots(t));
         static_assert(mg::kStats == MG_NSTATS, "stats layout");
         DevBuf d_work;
         const size_t stats_off = kQueueBytes + 8 * maxq;
@@ -1423,7 +1497,7 @@ int mg_count(const mg_graph *g, const mg_tree *tr_c, const mg_count_opts *opts,
         }
         struct Guard3 { DevBuf *b; ~Guard3() { dev_free(*b); } } gc{&d_cost};
 
-        std::vector<uint64_t> qcount(tr->distinct.size(), 0);
+        std::vector<uint64_t> qcount(n_slots(tr), 0);
         float total_ms = 0.f;
         mg_cursor cur{};
         for (size_t ri = 0; ri < runs.size(); ++ri) {
@@ -1460,7 +1534,7 @@ int mg_count(const mg_graph *g, const mg_tree *tr_c, const mg_count_opts *opts,
                     if (cur.head[i] < len) cur.done = 0;
                 }
             }
-            std::vector<uint64_t> h(t->distinct.size());
+            std::vector<uint64_t> h(n_slots(t));
             HIP_TRY(hipMemcpyAsync(h.data(), d_counts, 8 * h.size(), hipMemcpyDeviceToHost, st));
             std::vector<uint64_t> hs(mg::kStats, 0);
             if (d_stats)
@@ -1469,9 +1543,9 @@ int mg_count(const mg_graph *g, const mg_tree *tr_c, const mg_count_opts *opts,
             HIP_TRY(hipStreamSynchronize(st));
             for (int i = 0; i < mg::kStats; ++i) stats_sum[i] += hs[i];
             if (o.mode == MG_MODE_COMINE) qcount = h;
-            else qcount[ri] = h[0];
+            else std::copy(h.begin(), h.end(), qcount.begin() + ri * h.size());
         }
-        for (int32_t i = 0; i < tr->n_motifs; ++i) counts[i] = qcount[tr->motif_q[i]];
+        map_counts(tr, qcount.data(), counts);
         if (o.root_cost && g->E) {
             HIP_TRY(hipMemcpyAsync(o.root_cost, d_cost.ptr, sizeof(uint64_t) * (size_t)g->E,
                                    hipMemcpyDeviceToHost, st));

@@ -106,6 +106,54 @@ def test_medium_graph_all_modes(delta):
     assert np.array_equal(api.count(g, tr, roots=roots), oracle_counts(og, ms, delta, roots))
 
 
+@pytest.mark.parametrize("seed", range(3))
+def test_multi_window_tiny(seed):
+    """One search for several windows equals the oracle at every window, on
+    tiny graphs with forced ties, every motif with k <= 3 and sampled four-
+    and five-edge motifs, in co-mining and per-motif mode."""
+    rng = np.random.default_rng(400 + seed)
+    n = int(rng.integers(3, 8))
+    s, d, t = tiny_graph(rng, n, int(rng.integers(8, 16)), 10, self_loops=seed == 1)
+    og = OracleGraph(s, d, t, n)
+    ms = _tiny_motifs()
+    windows = [5, 0, BIG, 3, 1, 3]
+    want = np.stack([oracle_counts(og, ms, w) for w in windows])
+    g = api.Graph(s, d, t, n)
+    tr = api.Tree(ms, windows)
+    say("multi-window tiny", seed)
+    assert np.array_equal(api.count(g, tr), want)
+    assert np.array_equal(api.count(g, tr, mode="per_motif"), want)
+
+
+def test_multi_window_medium_every_path():
+    """Several windows on a medium graph through each leaf-counting path
+    (lane-counted, wave-counted, expanded), with statistics equal to a plain
+    search at the largest window, in a batch, and without allocation."""
+    s, d, t, n, ms = _medium(seed=2, E=6000, V=30, tmax=900)
+    windows = [40, 7, 19, 0]
+    og = OracleGraph(s, d, t, n)
+    want = np.stack([oracle_counts(og, ms, w) for w in windows])
+    g = api.Graph(s, d, t, n)
+    tr = api.Tree(ms, windows)
+    for ls in (0, 1, 4, -1):
+        say("multi-window medium leaf_scan", ls)
+        assert np.array_equal(api.count(g, tr, leaf_scan=ls), want), ls
+    _, st = api.count(g, tr, stats=True)
+    _, st1 = api.count(g, api.Tree(ms, max(windows)), stats=True)
+    assert st == st1
+    roots = np.arange(1, len(s), 3)
+    want_r = np.stack([oracle_counts(og, ms, w, roots) for w in windows])
+    assert np.array_equal(api.count(g, tr, roots=roots), want_r)
+    say("multi-window batch")
+    single = api.Tree(ms[:7], 11)
+    b = api.Batch([g, g], [tr, single], item_roots=128)
+    for _ in range(2):
+        a, c = b.count()
+        assert np.array_equal(a, want) and np.array_equal(c, oracle_counts(og, ms[:7], 11))
+    say("multi-window noalloc")
+    assert np.array_equal(api.count_noalloc(g, tr), want)
+
+
 def test_stop_and_resume():
     """A count stopped by a chunk budget and resumed from its cursor until
     done sums to the oracle's counts and statistics, on every root and on a
@@ -130,13 +178,15 @@ def test_stop_and_resume():
         calls = 0
         while not cur.done:
             flag = pinned if calls % 2 else stop
+            before = sum(cur.head)
             c, st = api.count(g, tr, roots=roots, queues=queues, max_chunks=budget,
                               stop=flag.data_ptr(), cursor=cur, stats=True)
             total += c
             for k, v in st.items():
                 st_total[k] = st_total.get(k, 0) + v
             calls += 1
-            assert calls < 10000
+            # every call with a budget searches at least one chunk, at most `budget`
+            assert before < sum(cur.head) <= before + 64 * budget
             if calls == 2:
                 # a raised flag: nothing is searched and the cursor stays
                 heads = list(cur.head)
@@ -322,6 +372,10 @@ def test_batch_equals_single_counts_and_oracle(gpu):
         assert info["graph_captured"] == (0 if kw.get("use_graph") is False else 1)
         assert info["n_jobs"] == len(graphs) and info["item_roots"] % 64 == 0
         b.close()
+    say("one-shot batch")
+    for kw in (dict(), dict(item_roots=128)):
+        for a, w in zip(api.count_batch(graphs, trees, **kw), want):
+            assert np.array_equal(a, w), kw
 
 
 @pytest.mark.parametrize("depth", [1, 2, 3, 5])
@@ -374,59 +428,6 @@ def test_config_minis(k, scale):
         assert np.array_equal(api.count(g, tr), want), (k, delta)
 
 
-def test_config2_full_size_sampled_roots():
-    """The benchmark's graph at full size (20M edges), launched exactly as the
-    benchmark launches it, checked on sampled roots the oracle can afford."""
-    wl = W.make_config(2)
-    s, d, t, n = wl.graphs[0]
-    ms, delta = wl.motif_sets[0], wl.deltas[0]
-    E = len(s)
-    rng = np.random.default_rng(0)
-    roots = np.concatenate([np.arange(q, q + 8192) for q in (0, E // 3, (2 * E) // 3, E - 8192)]
-                           + [np.sort(rng.choice(E, 16384, replace=False))])
-    og = OracleGraph(s, d, t, n)
-    want = oracle_counts(og, ms, delta, roots)
-    assert want.sum() > 0
-    g = api.Graph(s, d, t, n)
-    tr = api.Tree(ms, delta)
-    say("config2 full sampled")
-    assert np.array_equal(api.count(g, tr, roots=roots), want)
-    say("config2 full: co-mine vs per-motif on every root")
-    full = api.count(g, tr)
-    assert np.array_equal(api.count(g, tr, mode="per_motif"), full)
-    # single-edge count of the whole graph is the number of non-self-loop edges
-    one = api.count(g, api.Tree([[(0, 1)]], delta))
-    assert int(one[0]) == int((s != d).sum())
-
-
-@pytest.mark.parametrize("k,scale,n_sample", [(4, 1.0, 2048), (5, 0.1, 4096), (3, 1.0, 0)])
-def test_large_configs_sampled_roots(k, scale, n_sample):
-    """Configuration-scale graphs (config 4 at full size, 50M edges; config 5
-    at a tenth; config 3's largest graphs), counts on sampled roots against
-    the oracle, plus co-mine == per-motif on the sample."""
-    wl = W.make_config(k, scale=scale)
-    rng = np.random.default_rng(k)
-    jobs = list(range(len(wl.graphs)))
-    if k == 3:   # the three largest graphs of the batch
-        jobs = sorted(jobs, key=lambda j: -len(wl.graphs[j][0]))[:3]
-    for j in jobs:
-        s, d, t, n = wl.graphs[j]
-        ms = wl.motif_sets[j]
-        E = len(s)
-        ns = n_sample or 4096
-        roots = np.sort(rng.choice(E, min(E, ns), replace=False))
-        og = OracleGraph(s, d, t, n)
-        g = api.Graph(s, d, t, n)
-        for delta in wl.deltas if k == 5 else [wl.deltas[j]]:
-            tr = api.Tree(ms, delta)
-            say("config", k, "job", j, "E", E, "delta", delta)
-            want = oracle_counts(og, ms, delta, roots)
-            assert np.array_equal(api.count(g, tr, roots=roots), want), (k, j, delta)
-            assert np.array_equal(api.count(g, tr, roots=roots, mode="per_motif"), want)
-        og.close()
-        g.close()
-
-
 def test_edge_cases(oracle_mod):
     ms = [[(0, 1)], [(0, 1), (1, 2)], [(0, 1), (2, 3), (1, 2)]]
     # empty graph
@@ -466,6 +467,25 @@ def test_edge_cases(oracle_mod):
     got = gpu_count(s[perm], d[perm], t[perm], 9, ms, 6)
     og2 = OracleGraph(s[perm], d[perm], t[perm], 9)
     assert np.array_equal(got, oracle_counts(og2, ms, 6))
+
+
+def test_device_input_graph(gpu):
+    """Edges handed over in device memory (MG_DEVICE_INPUT) give the same graph
+    and counts as host arrays, sorted or not."""
+    rng = np.random.default_rng(9)
+    s, d, t = tiny_graph(rng, 20, 2000, 300, self_loops=True)
+    ms = W.random_extension_motifs(10, (2, 3, 4), 5, 9)
+    og = OracleGraph(s, d, t, 20)
+    want = oracle_counts(og, ms, 30)
+    tr = api.Tree(ms, 30)
+    for perm in (np.arange(len(s)), rng.permutation(len(s))):
+        say("device input")
+        g = api.Graph(*(gpu.from_numpy(np.ascontiguousarray(x[perm])).cuda() for x in (s, d, t)), 20)
+        assert g.info()["n_edges"] == len(s) and g.info()["self_loops"] == int((s == d).sum())
+        assert np.array_equal(api.count(g, tr), want)
+    with pytest.raises(api.MayuraError, match="MG_EINVAL"):
+        bad = gpu.from_numpy(np.array([0, 25], np.int32)).cuda()
+        api.Graph(bad, bad.flip(0), gpu.zeros(2, dtype=gpu.int64, device="cuda"), 20)
 
 
 def test_wide_time_span_uses_64bit_times():

@@ -92,3 +92,25 @@ def test_count_rejects_null(L):
     assert L.mg_count(None, None, None, None) == -1
     L.mg_graph_destroy(None)
     L.mg_tree_destroy(None)
+
+
+def test_multi_window_trees():
+    """Several windows in one tree: one search shape, the largest window as
+    the tree's delta, windows in any order with duplicates allowed."""
+    ms = W.enumerate_motifs(3, 3)
+    t = api.Tree(ms, [3600, 900, 21600, 900])
+    i = t.info()
+    assert (i["n_deltas"], i["delta"], i["n_nodes"]) == (4, 21600, 43)
+    assert {k: v for k, v in i.items() if k not in ("n_deltas", "delta")} == \
+        {k: v for k, v in info(ms).items() if k not in ("n_deltas", "delta")}
+    assert api.Tree(ms, 5).info()["n_deltas"] == 1
+    with pytest.raises(api.MayuraError, match="MG_EINVAL"):
+        api.Tree(ms, [5, -1])
+    with pytest.raises(api.MayuraError, match="MG_EINVAL"):
+        api.Tree(ms, [])
+    with pytest.raises(api.MayuraError, match="MG_EUNSUPPORTED"):
+        api.Tree(ms, list(range(9)))                    # more than MG_MAX_DELTAS
+    big = W.enumerate_motifs(3, 4) + W.enumerate_motifs(4, 4)   # 756 motifs
+    api.Tree(big, [1, 2, 3, 4, 5])                      # 3,780 counters
+    with pytest.raises(api.MayuraError, match="MG_EUNSUPPORTED"):
+        api.Tree(big, [1, 2, 3, 4, 5, 6])               # 4,536 > 4,096 counters
