@@ -20,7 +20,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # HBM counter summary of the search kernel on this workload (rocprofv3 --pmc)
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "comine_kernel_powerlaw20M_36motifs_hbm_counters.md")
-KERNEL_SOURCES = ("comine.hip", "comine.h", "device_util.h")
+KERNEL_SOURCES = ("search.h", "comine.hip", "comine.h", "device_util.h")
 
 
 def log(*a):
@@ -349,6 +349,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--queues", type=int, default=0, help="root queues (0 = one per XCD)")
     ap.add_argument("--chunk", type=int, default=0, help="roots per queue grab (0 = default)")
+    ap.add_argument("--no-tune", action="store_true", help="default launch settings, no autotuner")
     ap.add_argument("--config", type=int, default=2, choices=(2, 3, 4, 5),
                     help="2: the headline single-graph benchmark (default); 3: batched; "
                          "4: learned schedule; 5: learned + batched delta sweep")
@@ -404,6 +405,13 @@ def main():
     log("stats", st, "algorithmic bytes/launch %.3e (narrow model %.3e)" % (algo_bytes, algo_narrow))
 
     kw = dict(queues=args.queues, chunk=args.chunk)
+    tuning = None
+    if not args.no_tune and not (args.queues or args.chunk):
+        # the autotuner times the launch settings (roots per chunk, queues,
+        # leaf-count limit, workgroups) on this graph and tree
+        tuning = api.tune(g, tr)
+        kw = {k: tuning[k] for k in ("blocks", "chunk", "queues", "leaf_scan")}
+        log("tuned", tuning)
     for _ in range(args.warmup):
         api.count(g, tr, **kw)
     torch.cuda.synchronize()
@@ -485,6 +493,7 @@ def main():
                          "co-mining speedups on real graphs",
         "roofline": roofline,
         "stats": st,
+        "tuning": tuning,
         "total_matches": int(counts.sum()),
     }
     if not args.no_cpu_baseline:

@@ -262,6 +262,29 @@ int mg_count_noalloc(const mg_graph *g, const mg_tree *tr, const mg_count_opts *
                      uint64_t *counts);
 
 /*
+ * Autotuner (not in the paper): picks the launch settings of mg_count for a
+ * (graph, tree, device) by timing plain co-mining counts: the leaf-count
+ * limit (leaf_scan), roots per chunk, root queues and workgroups, one at a
+ * time from the defaults (coordinate descent, two sweeps at most, a setting
+ * kept only when it is more than 2 % faster).  Counts never depend on these
+ * settings.
+ *   cache_path : NULL, or a file of one JSON object per line keyed by the
+ *                graph's and tree's statistics and the device: a cached entry
+ *                is returned without timing; a new result is appended
+ *   out        : the chosen settings (copy them into mg_count_opts), their
+ *                time and that of the defaults
+ */
+typedef struct {
+    int32_t blocks, chunk, queues, leaf_scan;   /* the settings */
+    float ms;                 /* median search time with them */
+    float default_ms;         /* the same with the defaults */
+    int32_t from_cache;       /* 1 when read from the cache */
+    int32_t trials;           /* settings timed (0 from the cache) */
+} mg_tune_result;
+int mg_tune(const mg_graph *g, const mg_tree *tr, const char *cache_path, void *stream,
+            mg_tune_result *out);
+
+/*
  * Learned root-cost model (not in the paper): a 4-layer MLP, 16 -> 64 -> 64 ->
  * 64 -> 1 with ReLU, BF16 weights and activations, FP32 accumulation (MFMA),
  * that predicts log(1 + candidate edges examined below a root) -- the label

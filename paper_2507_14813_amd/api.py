@@ -61,6 +61,13 @@ class CountOpts(ctypes.Structure):
                 ("cursor", ctypes.c_void_p)]
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("blocks", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("queues", ctypes.c_int32), ("leaf_scan", ctypes.c_int32),
+                ("ms", ctypes.c_float), ("default_ms", ctypes.c_float),
+                ("from_cache", ctypes.c_int32), ("trials", ctypes.c_int32)]
+
+
 class Cursor(ctypes.Structure):
     """Resume point of a stopped count (``mg_cursor``)."""
     _fields_ = [("head", ctypes.c_uint64 * 8), ("n_roots", ctypes.c_int64),
@@ -138,6 +145,7 @@ def lib():
         L.mg_cursor_init.argtypes = [p]
         L.mg_cursor_init.restype = None
         L.mg_count_noalloc.argtypes = [p, p, ctypes.POINTER(CountOpts), p]
+        L.mg_tune.argtypes = [p, p, ctypes.c_char_p, p, ctypes.POINTER(TuneResult)]
         L.mg_last_error.restype = ctypes.c_char_p
         L.mg_model_create.argtypes = [ctypes.c_uint64, ctypes.POINTER(p)]
         L.mg_model_get_weights.argtypes = [p, p]
@@ -157,7 +165,7 @@ def lib():
         L.mg_batch_destroy.restype = None
         L.mg_count_batch.argtypes = [p, p, i32, ctypes.POINTER(BatchOpts), p]
         for f in ("mg_set_allocator", "mg_graph_create", "mg_graph_info",
-                  "mg_tree_create", "mg_tree_create_multi", "mg_tree_info", "mg_count", "mg_count_noalloc", "mg_batch_create",
+                  "mg_tree_create", "mg_tree_create_multi", "mg_tree_info", "mg_count", "mg_count_noalloc", "mg_tune", "mg_batch_create",
                   "mg_batch_count", "mg_batch_info", "mg_count_batch", "mg_model_create", "mg_model_get_weights",
                   "mg_model_set_weights", "mg_model_get_moments", "mg_root_features", "mg_model_predict",
                   "mg_model_train"):
@@ -365,6 +373,17 @@ def count(graph: Graph, tree: Tree, mode="comine", roots=None, blocks=0, chunk=0
     if root_cost:
         res.append(rcost[:graph.n_edges])
     return res[0] if len(res) == 1 else tuple(res)
+
+
+def tune(graph: Graph, tree: Tree, cache=None, stream=None):
+    """``mg_tune``: launch settings for ``count`` (a dict with blocks, chunk,
+    queues, leaf_scan), plus the timings, read from or appended to the JSON
+    lines file ``cache`` when given."""
+    r = TuneResult()
+    _check(lib().mg_tune(graph.handle, tree.handle,
+                         None if cache is None else os.fsencode(cache),
+                         _default_stream(stream), ctypes.byref(r)))
+    return {f: getattr(r, f) for f, _ in TuneResult._fields_}
 
 
 def count_noalloc(graph: Graph, tree: Tree, blocks=0, chunk=0, queues=0, stream=None,

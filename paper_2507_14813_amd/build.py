@@ -31,20 +31,31 @@ def _run(cmd):
     return out
 
 
-def build(verbose: bool = False) -> str:
+# the search kernels: one file per (tree depth, time width), largest first
+HIP_SOURCES = tuple("search_d%d_t%d.hip" % (d, t) for d in (5, 4, 3, 2, 1) for t in (32, 64)) + \
+    ("comine.hip", "sched.hip")
+
+
+def _compile(name):
+    obj = os.path.join(BUILD_DIR, name + ".o")
+    if name.endswith(".hip"):
+        cmd = [HIPCC, "-x", "hip", "--offload-arch=" + ARCH, *COMMON, *NO_PK_FP32]
+    else:   # host-only C++ (HIP runtime API, no device code)
+        cmd = [HIPCC, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I" + ROCM_INC, *COMMON]
+    return obj, _run(cmd + ["-c", os.path.join(CSRC, name), "-o", obj])
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every source (in parallel: one process per file, the tree
+    depths in separate files) and link libmayura.so."""
+    from concurrent.futures import ThreadPoolExecutor
     os.makedirs(BUILD_DIR, exist_ok=True)
+    names = list(HIP_SOURCES) + ["host.cpp"]
+    jobs = jobs or min(len(names), max(1, os.cpu_count() or 1))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        results = list(ex.map(_compile, names))
     objs = []
-    for name in ("comine.hip", "sched.hip"):
-        obj = os.path.join(BUILD_DIR, name + ".o")
-        out = _run([HIPCC, "-x", "hip", "--offload-arch=" + ARCH, *COMMON, *NO_PK_FP32,
-                    "-c", os.path.join(CSRC, name), "-o", obj])
-        if verbose and out:
-            print(out)
-        objs.append(obj)
-    for name in ("host.cpp",):   # host-only C++ (HIP runtime API, no device code)
-        obj = os.path.join(BUILD_DIR, name + ".o")
-        out = _run([HIPCC, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I" + ROCM_INC, *COMMON, "-c",
-                    os.path.join(CSRC, name), "-o", obj])
+    for obj, out in results:
         if verbose and out:
             print(out)
         objs.append(obj)

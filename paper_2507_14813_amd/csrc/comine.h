@@ -40,9 +40,11 @@ enum : int { kDirOut = 0, kDirIn = 1, kDirAll = 2 };
 //   inode[i]  internal (non-leaf) trie node i: first group | group count << 20
 //             | count of the leading groups on a list of motif vertex 0 or 1 << 26
 //   grp[2g], grp[2g+1]: eight words of group g:
-//     w0 = dir | anchor << 4 | nv << 8 | leaf_only << 12
+//     w0 = dir | anchor << 4 | nv << 8 | leaf_only << 12 | last_end << 13
 //          (nv: vertices bound at the owning node; leaf_only: a per-vertex
-//          list whose children all end a motif)
+//          list whose children all end a motif; last_end: the anchor is the
+//          source (1) or destination (2) of the owning node's last edge, 0
+//          otherwise)
 //     w1..w6 = child reached when the scanned endpoint is bound motif vertex 0..5
 //     w7 = child reached when the scanned endpoint(s) are new vertices
 //   A child word is 0 when there is no such child, else
@@ -73,8 +75,11 @@ template <typename TT>
 struct DevGraph {
     const int32_t *gsrc, *gdst;   // time-sorted edge list (all edges)
     const TT *gt;
-    const uint2 *gpos;            // per edge: its index in out_adj and in in_adj
-                                  // (self-loops: unused)
+    const uint4 *gx;              // per edge u -> v at t: the first index with a later
+                                  // time in out(u), in(u), out(v), in(v) (self-loops:
+                                  // unused)
+    const uint32_t *out_eid;      // edge id of every out_adj entry
+    const uint32_t *in_eid;       // edge id of every in_adj entry
     const uint32_t *out_off;      // V+1
     const Entry<TT> *out_adj;     // out-lists: destination, time
     const uint32_t *in_off;
@@ -160,6 +165,13 @@ struct BatchParams {
 // `depth` = the deepest tree of the batch.
 template <typename TT>
 hipError_t launch_batch(const BatchParams<TT> &bp, int depth, int blocks, hipStream_t stream);
+
+// The same for one tree depth D (search.h; instantiated in search_d<D>_t<bits>.hip).
+// MODE 0 is the plain search, 3 the search of trees with several windows.
+template <typename TT, int D>
+hipError_t launch_d(const KParams<TT> &p, int blocks, hipStream_t stream);
+template <typename TT, int D, int MODE>
+hipError_t launch_batch_d(const BatchParams<TT> &bp, int blocks, hipStream_t stream);
 
 // Device scratch of the count that allocates nothing: queue words, then
 // kMaxQueries counters, then kStats statistics.  One array per device, held

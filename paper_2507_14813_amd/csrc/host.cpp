@@ -14,6 +14,7 @@
 #include <new>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/mayura.h"
@@ -108,15 +109,27 @@ struct mg_graph {
     int64_t t_min = 0, t_max = 0;
     int time_bytes = 4;
     int device = 0;
-    DevBuf gsrc, gdst, gt, gpos, out_off, out_adj, in_off, in_adj;
+    DevBuf gsrc, gdst, gt, gx, out_eid, in_eid, out_off, out_adj, in_off, in_adj;
     int64_t device_bytes = 0;
     ~mg_graph() {
-        for (DevBuf *b : {&gsrc, &gdst, &gt, &gpos, &out_off, &out_adj, &in_off, &in_adj})
+        for (DevBuf *b : {&gsrc, &gdst, &gt, &gx, &out_eid, &in_eid, &out_off, &out_adj, &in_off,
+                          &in_adj})
             dev_free(*b);
     }
 };
 
 namespace {
+
+// f(begin, end) over [0, n) in contiguous pieces on the host's cores
+template <typename F>
+void parallel_for(int64_t n, F f) {
+    const int64_t nt = std::max<int64_t>(1, std::min<int64_t>(std::thread::hardware_concurrency(),
+                                                                n / 65536 + 1));
+    std::vector<std::thread> th;
+    for (int64_t k = 0; k < nt; ++k)
+        th.emplace_back([&, k] { f(n * k / nt, n * (k + 1) / nt); });
+    for (auto &x : th) x.join();
+}
 
 template <typename TT>
 int upload_graph(mg_graph *g, const std::vector<int32_t> &s, const std::vector<int32_t> &d,
@@ -134,13 +147,13 @@ int upload_graph(mg_graph *g, const std::vector<int32_t> &s, const std::vector<i
     for (int32_t v = 0; v < V; ++v) { oo[v + 1] += oo[v]; io[v + 1] += io[v]; }
     const uint32_t A = oo[V];
     std::vector<mg::Entry<TT>> oadj(A), iadj(A);
-    std::vector<uint32_t> pos(2 * (size_t)E, 0);   // per edge: index in out_adj, in in_adj
+    std::vector<uint32_t> oeid(A), ieid(A);   // edge id of every list entry
     {
         std::vector<uint32_t> po(oo.begin(), oo.end() - 1), pi(io.begin(), io.end() - 1);
         for (int64_t i = 0; i < E; ++i) {
             if (s[i] == d[i]) continue;
-            pos[2 * i] = po[s[i]];
-            pos[2 * i + 1] = pi[d[i]];
+            oeid[po[s[i]]] = (uint32_t)i;
+            ieid[pi[d[i]]] = (uint32_t)i;
             mg::Entry<TT> &x = oadj[po[s[i]]++];
             std::memset(&x, 0, sizeof x);
             x.v = d[i]; x.t = rt[i];
@@ -149,11 +162,35 @@ int upload_graph(mg_graph *g, const std::vector<int32_t> &s, const std::vector<i
             y.v = s[i]; y.t = rt[i];
         }
     }
+    // per edge (u -> v at t): where the entries after time t start in out(u),
+    // in(u), out(v) and in(v) -- the first index with a later time
+    std::vector<uint32_t> gx(4 * (size_t)E, 0);
+    parallel_for(E, [&](int64_t i0, int64_t i1) {
+        auto after = [&](const std::vector<mg::Entry<TT>> &adj, const std::vector<uint32_t> &off,
+                         int32_t v, TT t) {
+            uint32_t lo = off[v], n = off[v + 1] - off[v];
+            while (n > 0) {
+                const uint32_t h = n >> 1;
+                if (adj[lo + h].t <= t) { lo += h + 1; n -= h + 1; }
+                else n = h;
+            }
+            return lo;
+        };
+        for (int64_t i = i0; i < i1; ++i) {
+            if (s[i] == d[i]) continue;
+            gx[4 * i + 0] = after(oadj, oo, s[i], rt[i]);
+            gx[4 * i + 1] = after(iadj, io, s[i], rt[i]);
+            gx[4 * i + 2] = after(oadj, oo, d[i], rt[i]);
+            gx[4 * i + 3] = after(iadj, io, d[i], rt[i]);
+        }
+    });
     struct Up { DevBuf *b; const void *h; size_t n; };
     Up ups[] = {
         {&g->gsrc, s.data(), sizeof(int32_t) * E}, {&g->gdst, d.data(), sizeof(int32_t) * E},
         {&g->gt, rt.data(), sizeof(TT) * E},
-        {&g->gpos, pos.data(), sizeof(uint32_t) * 2 * E},
+        {&g->gx, gx.data(), sizeof(uint32_t) * 4 * E},
+        {&g->out_eid, oeid.data(), sizeof(uint32_t) * A},
+        {&g->in_eid, ieid.data(), sizeof(uint32_t) * A},
         {&g->out_off, oo.data(), sizeof(uint32_t) * (V + 1)},
         {&g->out_adj, oadj.data(), sizeof(mg::Entry<TT>) * A},
         {&g->in_off, io.data(), sizeof(uint32_t) * (V + 1)},
@@ -309,8 +346,14 @@ int build_tree(mg_tree *tr) {
         for (auto &kv : ordered) {
             bool leaf_only = kv.first.first != mg::kDirAll;
             for (int c : kv.second) leaf_only = leaf_only && tr->nodes[c].kids.empty();
-            int32_t rec[8] = {kv.first.first | (kv.first.second << 4) | (nd.nv << 8) |
-                                  ((leaf_only ? 1 : 0) << 12),
+            // the anchor is the source (1) or destination (2) of the node's
+            // own last edge: the window then starts where that edge's time
+            // ends in the anchor's list, known per edge
+            const int anc = kv.first.second;
+            const int last_end = kv.first.first == mg::kDirAll ? 0
+                                 : anc == nd.u ? 1 : anc == nd.v ? 2 : 0;
+            int32_t rec[8] = {kv.first.first | (anc << 4) | (nd.nv << 8) |
+                                  ((leaf_only ? 1 : 0) << 12) | (last_end << 13),
                               0, 0, 0, 0, 0, 0, 0};
             for (int c : kv.second) {
                 const TrieNode &ch = tr->nodes[c];
@@ -542,7 +585,9 @@ mg::DevGraph<TT> dev_graph(const mg_graph *g) {
     d.gsrc = (const int32_t *)g->gsrc.ptr;
     d.gdst = (const int32_t *)g->gdst.ptr;
     d.gt = (const TT *)g->gt.ptr;
-    d.gpos = (const uint2 *)g->gpos.ptr;
+    d.gx = (const uint4 *)g->gx.ptr;
+    d.out_eid = (const uint32_t *)g->out_eid.ptr;
+    d.in_eid = (const uint32_t *)g->in_eid.ptr;
     d.out_off = (const uint32_t *)g->out_off.ptr;
     d.out_adj = (const mg::Entry<TT> *)g->out_adj.ptr;
     d.in_off = (const uint32_t *)g->in_off.ptr;
@@ -1554,6 +1599,159 @@ int mg_count(const mg_graph *g, const mg_tree *tr_c, const mg_count_opts *opts,
         if (o.elapsed_ms) *o.elapsed_ms = total_ms;
         if (o.stats) std::copy(stats_sum.begin(), stats_sum.end(), o.stats);
         if (o.cursor) *o.cursor = cur;
+        return MG_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(MG_ENOMEM, "out of host memory");
+    } catch (...) {
+        return fail(MG_EINTERNAL, "unexpected exception");
+    }
+}
+
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- autotuner
+namespace {
+
+// Identity of a (graph, tree, device) for the tuning cache: the graph's and
+// tree's statistics and the device's name and compute-unit count.
+std::string tune_key(const mg_graph *g, const mg_tree *tr) {
+    hipDeviceProp_t prop{};
+    if (hipGetDeviceProperties(&prop, g->device) != hipSuccess) prop.name[0] = 0;
+    uint64_t h = 1469598103934665603ull;   // FNV-1a over the relabelled motifs
+    auto mix = [&](uint64_t x) { h = (h ^ x) * 1099511628211ull; };
+    for (const Motif &m : tr->distinct) {
+        mix(m.size());
+        for (auto &e : m) mix((uint64_t)e.first << 8 | (uint64_t)e.second);
+    }
+    for (int64_t w : tr->deltas) mix((uint64_t)w);
+    char buf[512];
+    snprintf(buf, sizeof buf, "%s/%d|E=%lld|V=%d|span=%lld|tb=%d|loops=%lld|motifs=%zu|depth=%d|"
+             "prefixes=%d|trees=%016llx", prop.name, prop.multiProcessorCount, (long long)g->E,
+             g->V, (long long)(g->t_max - g->t_min), g->time_bytes, (long long)g->self_loops,
+             tr->distinct.size(), tr->depth, tr->info.n_prefixes, (unsigned long long)h);
+    std::string k(buf);
+    for (char &c : k)
+        if (c == '"' || c == '\\' || c == '\n') c = '_';
+    return k;
+}
+
+// One cache line: {"key": "...", "blocks": b, "chunk": c, "queues": q, "leaf_scan": l, "ms": t}
+bool cache_lookup(const char *path, const std::string &key, mg_tune_result *r) {
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    char line[1024];
+    bool found = false;
+    const std::string want = "{\"key\": \"" + key + "\"";
+    while (fgets(line, sizeof line, f)) {
+        if (strncmp(line, want.c_str(), want.size()) != 0 || line[want.size()] != ',') continue;
+        mg_tune_result t{};
+        if (sscanf(line + want.size(),
+                   ", \"blocks\": %d, \"chunk\": %d, \"queues\": %d, \"leaf_scan\": %d, "
+                   "\"ms\": %f, \"default_ms\": %f",
+                   &t.blocks, &t.chunk, &t.queues, &t.leaf_scan, &t.ms, &t.default_ms) == 6) {
+            *r = t;
+            found = true;   // the last entry for a key wins
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+int cache_store(const char *path, const std::string &key, const mg_tune_result &r) {
+    FILE *f = fopen(path, "a");
+    if (!f) return fail(MG_EINVAL, "cannot append to the tuning cache %s", path);
+    fprintf(f,
+            "{\"key\": \"%s\", \"blocks\": %d, \"chunk\": %d, \"queues\": %d, \"leaf_scan\": %d, "
+            "\"ms\": %.4f, \"default_ms\": %.4f}\n",
+            key.c_str(), r.blocks, r.chunk, r.queues, r.leaf_scan, r.ms, r.default_ms);
+    fclose(f);
+    return MG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mg_tune(const mg_graph *g, const mg_tree *tr, const char *cache_path, void *stream,
+            mg_tune_result *out) {
+    try {
+        if (!g || !tr || !out) return fail(MG_EINVAL, "NULL argument");
+        const std::string key = tune_key(g, tr);
+        mg_tune_result best{};
+        if (cache_path && cache_lookup(cache_path, key, &best)) {
+            best.from_cache = 1;
+            *out = best;
+            return MG_OK;
+        }
+        int dev = 0, ncu = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+        // median of three timed counts after one untimed one
+        int32_t trials = 0;
+        auto time_of = [&](const mg_tune_result &c, float *ms) -> int {
+            mg_count_opts o;
+            mg_count_opts_init(&o);
+            o.blocks = c.blocks;
+            o.chunk = c.chunk;
+            o.queues = c.queues;
+            o.leaf_scan = c.leaf_scan;
+            o.stream = stream;
+            std::vector<uint64_t> cnt((size_t)tr->n_motifs * tr->delta_slot.size());
+            int rc = mg_count(g, tr, &o, cnt.data());
+            if (rc) return rc;
+            float t[3];
+            o.elapsed_ms = nullptr;
+            for (float &x : t) {
+                o.elapsed_ms = &x;
+                rc = mg_count(g, tr, &o, cnt.data());
+                if (rc) return rc;
+            }
+            std::sort(t, t + 3);
+            *ms = t[1];
+            ++trials;
+            return MG_OK;
+        };
+        // coordinate descent from the defaults, one setting at a time
+        mg_tune_result cur{};
+        cur.blocks = 0;
+        cur.chunk = 64;
+        cur.queues = mg::kQueues;
+        cur.leaf_scan = (int32_t)mg::kLeafScanDefault;
+        int rc = time_of(cur, &cur.ms);
+        if (rc) return rc;
+        cur.default_ms = cur.ms;
+        const std::vector<int32_t> chunks = {64, 128, 256}, queues = {8, 4, 2, 1},
+                                   scans = {64, 128, 256, 512, 1024},
+                                   blocks = {0, ncu * 4, ncu * 6};
+        for (int sweep = 0; sweep < 2; ++sweep) {
+            bool moved = false;
+            for (int dim = 0; dim < 4; ++dim) {
+                const std::vector<int32_t> &vals =
+                    dim == 0 ? scans : dim == 1 ? chunks : dim == 2 ? queues : blocks;
+                for (int32_t v : vals) {
+                    mg_tune_result c = cur;
+                    int32_t &field = dim == 0 ? c.leaf_scan : dim == 1 ? c.chunk
+                                     : dim == 2 ? c.queues : c.blocks;
+                    if (field == v) continue;
+                    field = v;
+                    rc = time_of(c, &c.ms);
+                    if (rc) return rc;
+                    // a new setting must win by more than the noise of one timing
+                    if (c.ms < 0.98f * cur.ms) {
+                        cur = c;
+                        moved = true;
+                    }
+                }
+            }
+            if (!moved) break;
+        }
+        cur.trials = trials;
+        if (cache_path) {
+            rc = cache_store(cache_path, key, cur);
+            if (rc) return rc;
+        }
+        *out = cur;
         return MG_OK;
     } catch (const std::bad_alloc &) {
         return fail(MG_ENOMEM, "out of host memory");

@@ -1,0 +1,997 @@
+// Co-mining kernel for gfx950 (CDNA4, wave64).  This header is included once
+// per tree depth by search_d<depth>_t<bits>.hip (one translation unit per tree depth and time width).
+//
+// What runs here is the co-mining recursion of the paper (Algorithm 3, built
+// on the per-motif matcher of Algorithm 1): from every root edge, partial
+// matches are extended edge by edge along the search levels of the motif
+// group's prefix trie; reaching a trie node credits every motif whose edge
+// sequence equals that prefix, and the same partial match then continues into
+// all of the node's children.
+//
+// How it is laid out for the hardware (not the paper's warp-per-candidate
+// design):
+//   * Every wave is an independent worker.  Root edges are split into eight
+//     contiguous (time-ordered) queues, one per XCD; a wave grabs chunks from
+//     its XCD's queue and steals from the others when it runs dry, so roots
+//     that are close in time, and the adjacency they read, share one L2.
+//   * Partial matches are buffered per search level in LDS.  For a batch of
+//     partial matches at level L, every (partial match, child group) pair is
+//     a window of one time-sorted adjacency list: the entries with
+//     t_prev < t <= t_first + delta, found by bisection.  Children that read
+//     the same list (same direction, same anchor vertex) form one group and
+//     share one scan of the window.
+//   * Windows are found from other windows where possible: a root's windows
+//     in out(a) and in(b) start just past the root edge's own list position,
+//     and a deeper window on a list of the root's two vertices lies inside the
+//     root's window on that list (kept in LDS), so it needs a short bisection
+//     and no search for its end.  Below the first level, the pairs on such
+//     lists are taken before the others, so the lanes of one pass run
+//     bisections of similar length.
+//   * A window whose children all end a motif is counted, not expanded: one
+//     equality count per bound vertex (the list's own anchor left out), the
+//     new-vertex child taking the rest; a short one by its own lane, a long
+//     one by the whole wave with ballots.
+//   * The other non-empty windows, up to 64 at a time, are expanded as one
+//     flat candidate range: lane i takes candidate c + i, finds its window
+//     from a 64-bit mask of window ends (LDS flags + ballot + popcount), reads
+//     one adjacency entry, finds which bound motif vertex it hits with
+//     predicated compares, picks the reached child from the group record
+//     (which also carries the child's motif id), credits LDS counters, and
+//     compacts the survivors that still have children into the next level's
+//     buffer with ballot + mbcnt.
+//   * When the next level's buffer holds 64 or more partial matches it is
+//     expanded at once (depth first over batches), so LDS use is bounded by
+//     the motif length, not by the size of the search tree.
+//   * The level loop nest is unrolled at compile time for the tree depth
+//     (1..5 motif edges), one instantiation per depth.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "comine.h"
+#include "device_util.h"
+
+namespace mg {
+namespace {
+
+
+constexpr uint32_t kChunkLimit = 0x7fffffffu;   // candidates per window chunk
+
+// child word of a group for scanned-endpoint index y (0..5 bound, else new)
+__device__ __forceinline__ uint32_t child_word(const uint4 &a, const uint4 &b, int y) {
+    uint32_t r = b.w;             // new vertex
+    r = (y == 0) ? a.y : r;
+    r = (y == 1) ? a.z : r;
+    r = (y == 2) ? a.w : r;
+    r = (y == 3) ? b.x : r;
+    r = (y == 4) ? b.y : r;
+    r = (y == 5) ? b.z : r;
+    return r;
+}
+
+// The smaller window j of a multi-window tree (selects, so that the
+// parameter array is never indexed at run time: a local copy of it would go
+// to scratch memory).
+template <typename TT>
+__device__ __forceinline__ TT window_lo(const KParams<TT> &p, uint32_t j) {
+    TT r = p.dlo[0];
+#pragma unroll
+    for (int i = 1; i < kMaxDeltas - 1; ++i) r = j == (uint32_t)i ? p.dlo[i] : r;
+    return r;
+}
+
+// Window slot of a match with first time tf and last time tl: the number of
+// smaller windows its span exceeds.
+template <typename TT>
+__device__ __forceinline__ uint32_t window_slot(const KParams<TT> &p, uint32_t nd, TT tf, TT tl) {
+    uint32_t j = 0;
+#pragma unroll
+    for (int i = 0; i < kMaxDeltas - 1; ++i)
+        j += ((uint32_t)i + 1 < nd && tl > sat_add(tf, p.dlo[i])) ? 1u : 0u;
+    return j;
+}
+
+// c matches of the child in `word`, credited to window slot j of its motif
+// (nd slots per motif).  With `move`, the c matches were already credited to
+// slot j + 1 (they lie in a larger window too) and move down to slot j: slot
+// j + 1 loses them.  The counters are summed over slots modulo 2^64, so a
+// slot may hold a negative amount in between.
+__device__ __forceinline__ uint32_t credit_child(uint32_t word, uint32_t c,
+                                                unsigned long long *cnt, uint32_t nd,
+                                                uint32_t j, bool move = false) {
+    if (!c || !word) return 0;
+    const uint32_t q1 = (word >> 16) & 0x7fffu;
+    if (q1) {
+        atomicAdd(&cnt[(q1 - 1) * nd + j], (unsigned long long)c);
+        if (move) atomicAdd(&cnt[(q1 - 1) * nd + j + 1], 0ull - c);
+    }
+    return move ? 0u : c;
+}
+
+// Counts a leaf-only window [l0, l0 + len) of one adjacency list for one
+// partial match: each entry reaches the child of the bound vertex it hits, or
+// the new-vertex child.  The bound vertices are distinct, so an entry hits at
+// most one of them: one equality count per bound vertex, and the new-vertex
+// child gets the rest of the window.  The list's own anchor is left out of
+// q[] (no entry equals it: lists hold no self-loops); q[0..K) are the other
+// bound vertices (-1 for none) and w[0..K) their child words, wn the
+// new-vertex child's word.  Credits go to window slot j of each motif (nd
+// slots per motif).  Returns the credits.
+template <int U, int K, typename TT, int N>
+__device__ __forceinline__ uint32_t leaf_count(const Entry<TT> *__restrict__ adj, uint32_t l0,
+                                               uint32_t len, const int32_t (&q)[N],
+                                               const uint32_t (&w)[N], uint32_t wn,
+                                               unsigned long long *cnt, uint32_t nd,
+                                               uint32_t j, bool move = false) {
+    static_assert(K <= N, "slots");
+    uint32_t c[K];
+#pragma unroll
+    for (int s = 0; s < K; ++s) c[s] = 0;
+    // U independent loads per step, the last step included: there an index
+    // past the window reloads its last entry (len >= 1) and counts as no hit,
+    // so a window of up to U entries costs one memory trip
+    const Entry<TT> *e = adj + l0;
+    uint32_t i = 0;
+    for (; i + U <= len; i += U) {
+        int32_t v[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) v[j] = e[i + j].v;
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+#pragma unroll
+            for (int s = 0; s < K; ++s) c[s] += v[j] == q[s];
+    }
+    if (i < len) {
+        int32_t v[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) v[j] = e[min(i + j, len - 1)].v;
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int32_t x = i + j < len ? v[j] : -2;   // -2 matches no vertex
+#pragma unroll
+            for (int s = 0; s < K; ++s) c[s] += x == q[s];
+        }
+    }
+    uint32_t hit = 0, got = 0;
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        hit += c[s];
+        got += credit_child(w[s], c[s], cnt, nd, j, move);
+    }
+    return got + credit_child(wn, len - hit, cnt, nd, j, move);
+}
+
+
+// Counts the leaf-only window [l0, l0 + len) of group g for the partial match
+// with bound vertices ph[] with the whole wave, 64 entries per pass: one ballot per bound
+// vertex counts the entries that hit it, and the new-vertex child gets the
+// rest.  All arguments are wave-uniform.  Credits go to window slot j.
+// Returns the credits on lane 0 (0 on the other lanes).
+template <typename TT, int SA>
+__device__ __forceinline__ uint32_t leaf_scan_wave(const KParams<TT> &p, const int32_t (&ph)[SA],
+                                                   uint32_t g, uint32_t l0, uint32_t len,
+                                                   const int lane, unsigned long long *cnt,
+                                                   uint32_t nd, uint32_t j, bool move = false) {
+    const uint4 ga = p.tree.grp[2 * g], gb = p.tree.grp[2 * g + 1];
+    const uint32_t nvp = (ga.x >> 8) & 15;
+    const Entry<TT> *__restrict__ e =
+        ((ga.x & 15) == kDirOut ? p.g.out_adj : p.g.in_adj) + l0;
+    int32_t q[SA];
+    uint32_t c[SA];
+#pragma unroll
+    for (int s = 0; s < SA; ++s) {
+        q[s] = (uint32_t)s < nvp ? ph[s] : -1;
+        c[s] = 0;
+    }
+    uint32_t i = 0;
+    for (; i + 4 * kWave <= len; i += 4 * kWave) {
+        int32_t v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = e[i + j * kWave + lane].v;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int s = 0; s < SA; ++s) c[s] += (uint32_t)__popcll(__ballot(v[j] == q[s]));
+    }
+    for (; i < len; i += kWave) {
+        const int32_t v = i + lane < len ? e[i + lane].v : -2;   // -2 matches no slot
+#pragma unroll
+        for (int s = 0; s < SA; ++s) c[s] += (uint32_t)__popcll(__ballot(v == q[s]));
+    }
+    if (lane != 0) return 0;
+    const uint32_t words[6] = {ga.y, ga.z, ga.w, gb.x, gb.y, gb.z};
+    uint32_t hit = 0, got = 0;
+#pragma unroll
+    for (int s = 0; s < SA; ++s) {
+        hit += c[s];
+        got += credit_child(words[s], c[s], cnt, nd, j, move);
+    }
+    return got + credit_child(gb.w, len - hit, cnt, nd, j, move);
+}
+
+// Partial matches with L motif edges matched.  Level 1 is the root batch:
+// every entry is at the trie root and its last edge is its first, so it keeps
+// only the two bound vertices and the root time.
+// (R: the per-root cost log keeps each partial match's root edge.)
+template <typename TT, int L, bool R>
+struct LevelBuf {
+    static constexpr int S = (2 * L < kVMax) ? 2 * L : kVMax;   // vertex slots
+    static constexpr int C = 2 * kWave;                          // capacity
+    // phi[s - 2][i]: graph vertex of motif vertex s >= 2; motif vertices 0 and
+    // 1 and t_first are the root's, kept once in the level-1 batch (slot r1)
+    int32_t phi[S - 2][C];
+    uint32_t eid[C];       // edge id of its last matched edge
+    uint16_t node[C];      // internal trie node reached
+    uint16_t pincl[C];     // inclusive prefix of child-group counts: groups on
+    uint16_t pincl1[C];    // lists of motif vertex 0 or 1, then the others
+    uint8_t r1[C];         // slot of its root in the level-1 batch
+    uint32_t root[R ? C : 1];
+};
+template <typename TT, bool R>
+struct LevelBuf<TT, 1, R> {
+    static constexpr int S = 2;
+    static constexpr int C = kWave;
+    int32_t phi[2][kWave];
+    TT tfirst[kWave];
+    uint32_t root[R ? kWave : 1];
+};
+
+template <typename TT, int D, bool R, int L>
+struct LevelChain {
+    LevelBuf<TT, L, R> buf;
+    LevelChain<TT, D, R, L + 1> next;
+};
+template <typename TT, int D, bool R>
+struct LevelChain<TT, D, R, D> {};
+
+// per-wave LDS: level buffers plus small scratch tables.  Its size is a
+// multiple of 16 bytes, so that per-wave blocks laid out back to back (with
+// 64-bit counters between them) keep those counters 8-byte aligned, as LDS
+// 64-bit atomics require.
+//
+// Root windows: for each root of the level-1 batch, the windows it found in
+// out(a), in(a), out(b), in(b) (index anchor * 2 + direction): first entry and
+// length, kNoHint as length when not found yet or 65535 entries or longer.  A deeper partial match of that root reads a window of the same
+// list with t_prev < t <= t_first + delta, t_prev > t_first: it starts inside
+// the root's window and ends where it ends, so a bisection over the root's
+// window replaces a bisection over the whole list and the search for the end.
+template <typename TT, int D, bool R>
+struct alignas(16) WaveLds {
+    static constexpr int H = D > 1 ? 4 : 1;
+    uint8_t src[kWave];           // window compaction: lane holding the k-th window
+    uint8_t flag[kWave];          // window-end marks of one pass
+    uint32_t hlo[H][kWave];       // root windows (used when D > 2)
+    uint16_t hlen[H][kWave];
+    LevelChain<TT, D, R, 1> lv;
+};
+
+static_assert(sizeof(WaveLds<uint32_t, 1, false>) % 16 == 0, "per-wave LDS block size");
+static_assert(sizeof(WaveLds<uint32_t, 3, false>) % 16 == 0, "per-wave LDS block size");
+static_assert(sizeof(WaveLds<uint32_t, 5, false>) % 16 == 0, "per-wave LDS block size");
+static_assert(sizeof(WaveLds<uint64_t, 5, true>) % 16 == 0, "per-wave LDS block size");
+
+constexpr uint16_t kNoHint = 0xffff;
+
+// A new root a -> b in level-1 slot `slot`: its root windows are not found
+// yet; their first-entry words hold where they start, the first entries
+// after the root's time in out(a), in(a), out(b) and in(b).
+template <typename TT, int D, bool R>
+__device__ __forceinline__ void set_root_slot(WaveLds<TT, D, R> &W, uint32_t slot, uint4 gx) {
+    W.hlo[0][slot] = gx.x;
+    W.hlo[1][slot] = gx.y;
+    W.hlo[2][slot] = gx.z;
+    W.hlo[3][slot] = gx.w;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) W.hlen[k][slot] = kNoHint;
+}
+
+template <int L, typename TT, int D, bool R, int M>
+__device__ __forceinline__ LevelBuf<TT, L, R> &lvl(LevelChain<TT, D, R, M> &c) {
+    if constexpr (L == M) return c.buf;
+    else return lvl<L>(c.next);
+}
+
+// per-lane statistics (only the STATS instantiation touches them)
+struct Stats {
+    uint64_t v[kStats];
+};
+
+// MODE: 0 plain search (trees with one window), 1 with search statistics, 2
+// with the per-root cost log, 3 plain search of a tree with several windows
+// At level 1 with nparts > 1 (one buffered root), only part `part` of the
+// root's candidates is expanded: [T * part / nparts, T * (part + 1) / nparts)
+// of its T candidates in window order, so that the parts of one root
+// partition its search exactly; windows that a single lane counts, and the
+// root's window statistics, belong to part 0.
+template <typename TT, int D, int MODE, int L>
+__device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, MODE == 2> &W,
+                                          unsigned long long *cnt, const int lane,
+                                          const uint32_t nA, Stats &st, const uint32_t part = 0,
+                                          const uint32_t nparts = 1) {
+    constexpr bool STATS = MODE == 1, LOG = MODE == 2;
+    LevelBuf<TT, L, LOG> &A = lvl<L>(W.lv);
+    constexpr int SA = LevelBuf<TT, L, LOG>::S;
+    LevelBuf<TT, 1, LOG> &R1 = lvl<1>(W.lv);
+    // graph vertex of motif vertex s, and t_first, of buffered partial match i
+    auto vtx = [&](uint32_t s, uint32_t i) -> int32_t {
+        if constexpr (L == 1) return A.phi[s][i];
+        else return s < 2 ? R1.phi[s][A.r1[i]] : A.phi[s < 2 ? 0 : s - 2][i];
+    };
+    auto tfirst_of = [&](uint32_t i) -> TT {
+        if constexpr (L == 1) return A.tfirst[i];
+        else return R1.tfirst[A.r1[i]];
+    };
+    const uint32_t *__restrict__ inode = p.tree.inode;
+    const uint4 *__restrict__ grp = p.tree.grp;
+    const uint64_t le_mask = (lane == 63) ? ~0ull : ((2ull << lane) - 1);
+    // windows counted at once (MODE 0 serves trees with one window only)
+    const uint32_t nd = MODE == 0 ? 1u : (uint32_t)p.tree.n_d;
+
+
+    // child groups per buffered partial match -> inclusive prefix (at the
+    // root level every entry has the root's groups).  Below it the pairs are
+    // taken in two classes: groups on a list of motif vertex 0 or 1 (windows
+    // found inside the root's windows: short bisections) first, then the
+    // others, so that the lanes of one pass do bisections of similar length
+    // (pairs are numbered over both classes: the first P0 are of the first, so
+    // only the pass across the boundary mixes them).
+    uint32_t P = 0, P0 = 0, P1 = 0;
+    const uint32_t root_ng = (inode[0] >> 20) & 63u;
+    if constexpr (L == 1) {
+        P = nA * root_ng;
+    } else {
+        for (uint32_t x0 = 0; x0 < nA; x0 += kWave) {
+            const uint32_t x = x0 + lane;
+            uint32_t n0 = 0, n1 = 0;
+            if (x < nA) {
+                const uint32_t w = inode[A.node[x]];
+                n0 = w >> 26;
+                n1 = ((w >> 20) & 63u) - n0;
+            }
+            const uint32_t i0 = incl_scan32(n0, lane) + P0;
+            const uint32_t i1 = incl_scan32(n1, lane) + P1;
+            if (x < nA) {
+                A.pincl[x] = (uint16_t)i0;
+                A.pincl1[x] = (uint16_t)i1;
+            }
+            P0 = lane_value(i0, kWave - 1);
+            P1 = lane_value(i1, kWave - 1);
+        }
+        P = P0 + P1;
+        wave_sync();
+    }
+
+    // window chunk: lane w < nw holds non-empty window w
+    //   wrec = {entry | group << 8, first list index, exclusive start, inclusive end}
+    uint4 wrec = make_uint4(0, 0, 0, 0);
+    uint32_t pc = 0, nw = 0, T = 0, cc = 0;
+    uint32_t nB = 0;   // partial matches buffered at level L+1
+
+    for (;;) {
+        bool done = false;
+        if (cc >= T) {
+            if (pc >= P) {
+                done = true;
+            } else {
+                // one (partial match, group) pair per lane -> its window
+                const uint32_t pi = pc + lane;
+                uint32_t len = 0, x = 0, g = 0, l0 = 0, hdr = 0;
+                bool all = false;
+                if (pi < P) {
+                    uint32_t lo = 0;
+                    if constexpr (L == 1) {
+                        lo = pi / root_ng;
+                        g = (inode[0] & 0xfffffu) + (pi - lo * root_ng);
+                    } else {
+                        const bool c1 = pi >= P0;   // second class
+                        const uint32_t pj = c1 ? pi - P0 : pi;
+                        const uint16_t *pin = c1 ? A.pincl1 : A.pincl;
+                        uint32_t n = nA;
+                        while (n > 0) {
+                            const uint32_t h = n >> 1;
+                            if (pin[lo + h] <= pj) { lo += h + 1; n -= h + 1; }
+                            else n = h;
+                        }
+                        const uint32_t before = lo ? pin[lo - 1] : 0u;
+                        const uint32_t w = inode[A.node[lo]];
+                        g = (w & 0xfffffu) + (c1 ? (w >> 26) : 0u) + (pj - before);
+                    }
+                    x = lo;
+                    hdr = grp[2 * g].x;
+                    const int dir = hdr & 15, anc = (hdr >> 4) & 15;
+                    const TT thi = sat_add(tfirst_of(lo), p.delta_sat);
+                    uint32_t b, e, sh;
+                    const TT *ta;
+                    bool hinted = false, known = false;
+                    if (dir == kDirAll) {
+                        b = 0; e = p.g.n_edges; ta = p.g.gt; sh = 0;
+                        all = true;
+                        if constexpr (L > 1) {
+                            // the whole-list window starts after the last edge
+                            // itself (past the entries with its time)
+                            b = A.eid[lo] + 1u;
+                        }
+                    } else {
+                        ta = times_of(dir == kDirOut ? p.g.out_adj : p.g.in_adj);
+                        sh = 1;
+                        if constexpr (L > 1 && D > 2) {
+                            if (anc < 2) {
+                                const uint32_t k = (uint32_t)anc * 2u + (uint32_t)dir;
+                                const uint32_t r1 = A.r1[lo];
+                                const uint32_t hl = W.hlen[k][r1];
+                                hinted = hl != kNoHint;
+                                b = W.hlo[k][r1];
+                                e = b + hl;
+                            }
+                        }
+                        if (!hinted) {
+                            const int32_t a = vtx((uint32_t)anc, lo);
+                            const uint32_t *off = dir == kDirOut ? p.g.out_off : p.g.in_off;
+                            b = off[a]; e = off[a + 1];
+                        }
+                        if constexpr (L == 1) {
+                            // the root edge's own entries: its windows start at
+                            // the first entry after its time (set with the root)
+                            l0 = W.hlo[(uint32_t)anc * 2u + (uint32_t)dir][lo];
+                            known = true;
+                        } else {
+                            // an anchor on the last matched edge: the window
+                            // starts where that edge's time ends in its list
+                            const uint32_t le = (hdr >> 13) & 3u;
+                            if (le) {
+                                const uint4 gx = p.g.gx[A.eid[lo]];
+                                l0 = le == 1 ? (dir == kDirOut ? gx.x : gx.y)
+                                             : (dir == kDirOut ? gx.z : gx.w);
+                                known = true;
+                            }
+                        }
+                    }
+                    if (!known) {
+                        TT tp;
+                        if constexpr (L == 1) tp = A.tfirst[lo];
+                        else tp = p.g.gt[A.eid[lo]];
+                        l0 = all && L > 1 ? gallop_greater(ta, sh, b, e, tp)
+                                          : first_greater(ta, sh, b, e, tp);
+                    }
+                    len = (hinted ? e : gallop_greater(ta, sh, l0, e, thi)) - l0;
+                    if constexpr (L == 1 && D > 2) {
+                        if (!all && anc < 2) {
+                            const uint32_t k = (uint32_t)anc * 2u + (uint32_t)dir;
+                            W.hlo[k][lo] = l0;
+                            W.hlen[k][lo] = len < kNoHint ? (uint16_t)len : kNoHint;
+                        }
+                    }
+                }
+                // take the longest prefix of pairs whose candidates stay below 2^31
+                // (always all of them when every window is under 2^25 entries;
+                // 32-bit sums are exact unless some window has 2^26 entries)
+                bool take = pi < P;
+                if (__ballot(len >= (1u << 25))) {
+                    const uint64_t incl64 = __ballot(len >= (1u << 26))
+                                                ? incl_scan64((uint64_t)len, lane)
+                                                : (uint64_t)incl_scan32(len, lane);
+                    take = take && incl64 <= kChunkLimit;
+                }
+                pc += uniform((uint32_t)__popcll(__ballot(take)));
+                const bool own = part == 0;   // this part keeps the per-window work
+                if constexpr (STATS) {
+                    if (take && own) {
+                        st.v[all ? kStatWinAll : kStatWinList] += 1;
+                        st.v[all ? kStatEntAll : kStatEntList] += len;
+                    }
+                }
+                if constexpr (LOG) {
+                    if (take && own && len > 0)
+                        atomicAdd(&p.root_cost[A.root[x]], (unsigned long long)len);
+                }
+                // a window whose children are all leaves is counted without
+                // the candidate expansion: a short one by its own lane, a long
+                // one by the whole wave
+                const bool leaf = take && len > 0 && p.leaf_scan && ((hdr >> 12) & 1);
+                const bool scanned = leaf && len <= p.leaf_scan;
+                const bool coop = leaf && len > p.leaf_scan;
+                // bound vertices to compare with, the anchor left out; the
+                // count loop is compiled for the wave's largest number
+                const uint32_t nq = scanned && own ? ((hdr >> 8) & 15) - 1u : 0u;
+                uint32_t nqm = 0;
+#pragma unroll
+                for (int k = 1; k < SA; ++k) nqm += __ballot(nq >= (uint32_t)k) ? 1u : 0u;
+                if (scanned && own) {
+                    constexpr int NQ = SA - 1;
+                    const uint32_t anc = (hdr >> 4) & 15;
+                    const uint4 ga = grp[2 * g], gb = grp[2 * g + 1];
+                    int32_t ph[SA];
+#pragma unroll
+                    for (int t = 0; t < SA; ++t) ph[t] = vtx(t, x);
+                    const uint32_t words[6] = {ga.y, ga.z, ga.w, gb.x, gb.y, gb.z};
+                    int32_t q[NQ];
+                    uint32_t w[NQ];
+#pragma unroll
+                    for (int i = 0; i < NQ; ++i) {
+                        // slot i below the anchor, slot i + 1 from it on
+                        const bool below = (uint32_t)i < anc, on = (uint32_t)i < nq;
+                        q[i] = on ? (below ? ph[i] : ph[i + 1]) : -1;
+                        w[i] = on ? (below ? words[i] : words[i + 1]) : 0u;
+                    }
+                    const Entry<TT> *adj = (hdr & 15) == kDirOut ? p.g.out_adj : p.g.in_adj;
+                    // loads per step (measured: 8 for trees up to depth 3, 4 deeper)
+                    constexpr int kLU = D <= 3 ? 8 : 4;
+                    auto count = [&](uint32_t n, uint32_t j, bool move) -> uint32_t {
+                        uint32_t c = 0;
+                        if constexpr (NQ >= 1) if (nqm == 1) c = leaf_count<kLU, 1>(adj, l0, n, q, w, gb.w, cnt, nd, j, move);
+                        if constexpr (NQ >= 2) if (nqm == 2) c = leaf_count<kLU, 2>(adj, l0, n, q, w, gb.w, cnt, nd, j, move);
+                        if constexpr (NQ >= 3) if (nqm == 3) c = leaf_count<kLU, 3>(adj, l0, n, q, w, gb.w, cnt, nd, j, move);
+                        if constexpr (NQ >= 4) if (nqm == 4) c = leaf_count<kLU, 4>(adj, l0, n, q, w, gb.w, cnt, nd, j, move);
+                        if constexpr (NQ >= 5) if (nqm == 5) c = leaf_count<kLU, 5>(adj, l0, n, q, w, gb.w, cnt, nd, j, move);
+                        return c;
+                    };
+                    // the whole window counts at the largest window
+                    const uint32_t c = count(len, nd - 1, false);
+                    if constexpr (MODE != 0) {
+                        // each smaller window is a prefix of this one: its
+                        // matches move down one slot (usually it is empty)
+                        const TT *ta = times_of(adj);
+                        const TT tf = tfirst_of(x);
+                        uint32_t e = l0 + len;
+                        for (uint32_t j = nd - 1; j-- > 0;) {
+                            e = gallop_greater(ta, 1, l0, e, sat_add(tf, window_lo(p, j)));
+                            if (e == l0) break;
+                            count(e - l0, j, true);
+                        }
+                    }
+                    if constexpr (STATS) st.v[kStatCredit] += c;
+                }
+                for (uint64_t cm = __ballot(coop && own); cm; cm &= cm - 1) {
+                    const int src = (int)__builtin_ctzll(cm);
+                    const uint32_t wx = __builtin_amdgcn_readlane(x, src);
+                    int32_t wph[SA];
+#pragma unroll
+                    for (int t = 0; t < SA; ++t) wph[t] = (int32_t)uniform((uint32_t)vtx(t, wx));
+                    const uint32_t wg = __builtin_amdgcn_readlane(g, src);
+                    const uint32_t wl0 = __builtin_amdgcn_readlane(l0, src);
+                    const uint32_t wlen = __builtin_amdgcn_readlane(len, src);
+                    const uint32_t c = leaf_scan_wave<TT, SA>(p, wph, wg, wl0, wlen, lane, cnt, nd,
+                                                              nd - 1);
+                    if constexpr (MODE != 0) {
+                        const TT *ta = times_of((grp[2 * wg].x & 15) == kDirOut ? p.g.out_adj
+                                                                                : p.g.in_adj);
+                        const TT tf = tfirst_of(wx);
+                        uint32_t e = wl0 + wlen;
+                        for (uint32_t j = nd - 1; j-- > 0;) {
+                            e = uniform(gallop_greater(ta, 1, wl0, e, sat_add(tf, window_lo(p, j))));
+                            if (e == wl0) break;
+                            leaf_scan_wave<TT, SA>(p, wph, wg, wl0, e - wl0, lane, cnt, nd, j, true);
+                        }
+                    }
+                    if constexpr (STATS) st.v[kStatCredit] += c;
+                }
+                // compact the other non-empty windows into lanes 0..nw-1; their
+                // candidate ranges are numbered without the leaf-counted ones
+                // (the chunk total stays below the limit checked above)
+                const bool keep = take && len > 0 && !leaf;
+                const uint64_t km = __ballot(keep);
+                nw = uniform((uint32_t)__popcll(km));
+                wrec = make_uint4(0, 0, 0, 0);
+                T = 0;
+                if (nw) {
+                    const uint32_t lk = keep ? len : 0u;
+                    const uint32_t incl = incl_scan32(lk, lane);
+                    if (keep) W.src[mbcnt(km)] = (uint8_t)lane;
+                    wave_sync();
+                    const int from = (uint32_t)lane < nw ? (int)W.src[lane] : lane;
+                    wave_sync();
+                    wrec.x = __shfl(x | (g << 8), from);
+                    wrec.y = __shfl(l0, from);
+                    wrec.z = __shfl(incl - lk, from);
+                    wrec.w = __shfl(incl, from);
+                    if ((uint32_t)lane >= nw) wrec = make_uint4(0, 0, 0, 0);
+                    T = lane_value(wrec.w, nw - 1);
+                }
+                cc = 0;
+                if (L == 1 && nparts > 1) {
+                    // one root, so every window fits this one chunk
+                    cc = (uint32_t)(((uint64_t)T * part) / nparts);
+                    T = (uint32_t)(((uint64_t)T * (part + 1)) / nparts);
+                }
+            }
+        }
+        if (!done && cc < T) {
+            const uint32_t f = cc + lane;
+            // owner window = number of windows that end at or before f
+            const uint32_t o0 = (uint32_t)__popcll(__ballot((uint32_t)lane < nw && wrec.w <= cc));
+            if ((uint32_t)lane < nw && wrec.w > cc && wrec.w - cc < (uint32_t)kWave)
+                W.flag[wrec.w - cc] = 1;
+            wave_sync();
+            const uint32_t fl = W.flag[lane];
+            W.flag[lane] = 0;
+            const uint64_t ends = __ballot(fl != 0);
+            wave_sync();
+            const int oi = (int)((o0 + (uint32_t)__popcll(ends & le_mask)) & 63);
+            const uint32_t oxg = __shfl(wrec.x, oi);
+            const uint32_t olo = __shfl(wrec.y, oi);
+            const uint32_t oex = __shfl(wrec.z, oi);
+            const bool valid = f < T;
+            const uint32_t ox = oxg & 255, og = oxg >> 8;
+            const uint32_t ei = olo + (f - oex);
+
+            uint32_t cw = 0;      // child word reached by this candidate
+            TT tn = 0;            // its time
+            int dir = 0;
+            uint32_t nvp = 0;
+            int32_t nv0 = -1, nv1 = -1;
+            int32_t ph[SA];
+#pragma unroll
+            for (int s = 0; s < SA; ++s) ph[s] = 0;
+            uint4 ga = make_uint4(0, 0, 0, 0), gb = ga;
+            if (valid) {
+                ga = grp[2 * og];
+                gb = grp[2 * og + 1];
+                dir = ga.x & 15;
+                nvp = (ga.x >> 8) & 15;
+#pragma unroll
+                for (int s = 0; s < SA; ++s) ph[s] = vtx(s, ox);
+                if (dir != kDirAll) {
+                    const Entry<TT> *adj = dir == kDirOut ? p.g.out_adj : p.g.in_adj;
+                    const Entry<TT> en = adj[ei];   // one load: vertex and time
+                    const int32_t v = en.v;
+                    tn = en.t;
+                    int y = -1;
+#pragma unroll
+                    for (int s = 0; s < SA; ++s) y = ((uint32_t)s < nvp && ph[s] == v) ? s : y;
+                    // in-groups have no bound-target children, so their words are 0
+                    cw = child_word(ga, gb, y);
+                    nv0 = v;
+                }
+            }
+            if (__ballot(valid && dir == kDirAll)) {
+                if (valid && dir == kDirAll) {
+                    const int32_t cs = p.g.gsrc[ei], cd = p.g.gdst[ei];
+                    bool hit = cs == cd;
+#pragma unroll
+                    for (int s = 0; s < SA; ++s)
+                        hit |= ((uint32_t)s < nvp && (ph[s] == cs || ph[s] == cd));
+                    cw = hit ? 0u : gb.w;
+                    nv0 = cs;
+                    nv1 = cd;
+                    tn = p.g.gt[ei];
+                }
+            }
+            if (cw) {
+                const uint32_t q1 = (cw >> 16) & 0x7fffu;
+                if (q1) {
+                    const uint32_t j = nd > 1 ? window_slot(p, nd, tfirst_of(ox), tn) : 0u;
+                    atomicAdd(&cnt[(q1 - 1) * nd + j], 1ull);
+                }
+                if constexpr (STATS) st.v[kStatCredit] += 1;
+            }
+            if constexpr (L + 1 < D) {
+                LevelBuf<TT, L + 1, LOG> &B = lvl<L + 1>(W.lv);
+                constexpr int SB = LevelBuf<TT, L + 1, LOG>::S;
+                const bool push = (cw >> 31) != 0;
+                const uint64_t pm = __ballot(push);
+                if (push) {
+                    const uint32_t slot = nB + mbcnt(pm);
+#pragma unroll
+                    for (int s = 2; s < SB; ++s) {
+                        int32_t v = (s < SA) ? ph[s < SA ? s : 0] : -1;
+                        v = ((uint32_t)s < nvp) ? v
+                            : ((uint32_t)s == nvp ? nv0 : ((uint32_t)s == nvp + 1 ? nv1 : -1));
+                        B.phi[s - 2][slot] = v;
+                    }
+                    B.eid[slot] = dir == kDirAll ? ei
+                                                 : (dir == kDirOut ? p.g.out_eid : p.g.in_eid)[ei];
+                    B.node[slot] = (uint16_t)(cw & 0xffffu);
+                    if constexpr (L == 1) B.r1[slot] = (uint8_t)ox;
+                    else B.r1[slot] = A.r1[ox];
+                    if constexpr (LOG) B.root[slot] = A.root[ox];
+                    if constexpr (STATS) st.v[kStatPush] += 1;
+                }
+                nB += (uint32_t)__popcll(pm);
+            }
+            cc += kWave;
+        }
+        if constexpr (L + 1 < D) {
+            if (nB >= kWave || (done && nB > 0)) {
+                wave_sync();
+                run_level<TT, D, MODE, L + 1>(p, W, cnt, lane, nB, st);
+                wave_sync();
+                nB = 0;
+            }
+        }
+        if (done) break;
+    }
+}
+
+// Search from part `part` of `nparts` of the root at position r (an edge id:
+// split items come only with p.roots NULL); part 0 credits the root itself.
+template <typename TT, int D, int MODE>
+__device__ __forceinline__ void process_root_part(const KParams<TT> &p,
+                                                  WaveLds<TT, D, MODE == 2> &W,
+                                                  unsigned long long *cnt, const int lane,
+                                                  const uint32_t r, const uint32_t part,
+                                                  const uint32_t nparts, Stats &st) {
+    constexpr bool STATS = MODE == 1, LOG = MODE == 2;
+    const int32_t s = p.g.gsrc[r], d = p.g.gdst[r];
+    if (s == d) return;
+    if (part == 0) {
+        if (p.tree.root_q >= 0 && lane == 0) atomicAdd(&cnt[p.tree.root_q * p.tree.n_d], 1ull);
+        if constexpr (STATS) st.v[kStatRoots] += lane == 0 ? 1 : 0;
+        if constexpr (LOG) {
+            if (lane == 0) atomicAdd(&p.root_cost[r], 1ull);
+        }
+    }
+    if constexpr (D > 1) {
+        LevelBuf<TT, 1, LOG> &A = lvl<1>(W.lv);
+        if (lane == 0) {
+            A.phi[0][0] = s;
+            A.phi[1][0] = d;
+            A.tfirst[0] = p.g.gt[r];
+            set_root_slot(W, 0, p.g.gx[r]);
+            if constexpr (LOG) A.root[0] = r;
+        }
+        wave_sync();
+        run_level<TT, D, MODE, 1>(p, W, cnt, lane, 1u, st, part, nparts);
+        wave_sync();
+    }
+}
+
+// Search from roots [base, end) of the root list (positions, or edge ids when
+// p.roots is NULL), 64 at a time.
+template <typename TT, int D, int MODE>
+__device__ __forceinline__ void process_roots(const KParams<TT> &p,
+                                              WaveLds<TT, D, MODE == 2> &W,
+                                              unsigned long long *cnt, const int lane,
+                                              const uint32_t base, const uint32_t end,
+                                              Stats &st) {
+    constexpr bool STATS = MODE == 1, LOG = MODE == 2;
+    for (uint32_t b = base; b < end; b += kWave) {
+        const uint32_t i = b + (uint32_t)lane;
+        bool ok = i < end;
+        uint32_t r = 0;
+        int32_t s = 0, d = 0;
+        if (ok) {
+            r = p.roots ? p.roots[i] : i;
+            s = p.g.gsrc[r];
+            d = p.g.gdst[r];
+            ok = s != d;
+        }
+        const uint64_t m = __ballot(ok);
+        if (p.tree.root_q >= 0 && lane == 0 && m)
+            atomicAdd(&cnt[p.tree.root_q * p.tree.n_d], (unsigned long long)__popcll(m));
+        if constexpr (STATS) st.v[kStatRoots] += ok ? 1 : 0;
+        if constexpr (LOG) {
+            if (ok) atomicAdd(&p.root_cost[r], 1ull);
+        }
+        if constexpr (D > 1) {
+            LevelBuf<TT, 1, LOG> &A = lvl<1>(W.lv);
+            if (ok) {
+                const uint32_t slot = mbcnt(m);
+                A.phi[0][slot] = s;
+                A.phi[1][slot] = d;
+                A.tfirst[slot] = p.g.gt[r];
+                set_root_slot(W, slot, p.g.gx[r]);
+                if constexpr (LOG) A.root[slot] = r;
+            }
+            const uint32_t n1 = uniform((uint32_t)__popcll(m));
+            if (n1 > 0) {
+                wave_sync();
+                run_level<TT, D, MODE, 1>(p, W, cnt, lane, n1, st);
+                wave_sync();
+            }
+        }
+    }
+}
+
+// Up to depth 3 the plain search (MODE 0) fits 8 waves per SIMD (at most 64
+// VGPRs and 96 SGPRs) without spilling in its loops, and the multi-window
+// search (MODE 3) is faster there with a few spills than at 6 waves; the
+// compiler is asked for that.  Deeper trees and the instrumented modes keep
+// the compiler's own allocation.
+template <int D, int MODE>
+constexpr int min_waves_per_eu() { return D <= 3 && (MODE == 0 || MODE == 3) ? 8 : 1; }
+
+template <typename TT, int D, int MODE>
+__global__ void __launch_bounds__(kWave * kWavesPerBlock)
+__attribute__((amdgpu_waves_per_eu(min_waves_per_eu<D, MODE>(), 8)))
+comine_kernel(const KParams<TT> p) {
+    constexpr bool STATS = MODE == 1, LOG = MODE == 2;
+    extern __shared__ __align__(16) unsigned char smem[];
+    unsigned long long *cnt = reinterpret_cast<unsigned long long *>(smem);
+    const int32_t n_slots = counter_slots(p.tree);
+    const size_t cnt_bytes = ((size_t)n_slots * 8 + 15) & ~(size_t)15;
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const int wave = (int)(threadIdx.x / kWave);
+    WaveLds<TT, D, LOG> &W = reinterpret_cast<WaveLds<TT, D, LOG> *>(smem + cnt_bytes)[wave];
+
+    for (int i = (int)threadIdx.x; i < n_slots; i += (int)blockDim.x) cnt[i] = 0;
+    W.flag[lane] = 0;
+    __syncthreads();
+    Stats st;
+#pragma unroll
+    for (int i = 0; i < kStats; ++i) st.v[i] = 0;
+
+    if (p.items) {
+        // scheduled work items first, claimed in order from their own queue
+        const uint32_t n_items = uniform(*p.n_items);
+        for (;;) {
+            unsigned long long it = 0;
+            if (lane == 0) it = atomicAdd(&p.queues[kItemSlot * kQueueStride], 1ull);
+            it = lane0_u64(it);
+            if (it >= n_items) break;
+            const uint2 item = p.items[uniform((uint32_t)it)];
+            const uint32_t iy = uniform(item.y);
+            if (iy & kItemSplit)
+                process_root_part<TT, D, MODE>(p, W, cnt, lane, uniform(item.x),
+                                               (iy >> 15) & 0x7fffu, iy & 0x7fffu, st);
+            else
+                process_roots<TT, D, MODE>(p, W, cnt, lane, uniform(item.x), iy, st);
+        }
+    }
+    // workgroups are dispatched to the XCDs round-robin: start on this XCD's
+    // share of the roots, then take what is left of the others.  A chunk once
+    // claimed is always searched to the end, so after a stop the queue heads
+    // (clamped to the queue lengths) mark exactly the roots searched.
+    const uint32_t nq = p.n_queues;
+    const uint32_t home = blockIdx.x % nq;
+    bool stopped = false;
+    for (uint32_t qi = 0; qi < nq && !stopped; ++qi) {
+        const uint32_t q = (home + qi) % nq;
+        const uint32_t qbeg = queue_begin(p.n_roots, nq, q);
+        const uint32_t qend = queue_end(p.n_roots, nq, q);
+        for (;;) {
+            unsigned long long got = 0;
+            if (lane == 0) {
+                unsigned long long *head = &p.queues[q * kQueueStride];
+                if (p.stop && __hip_atomic_load(p.stop, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_SYSTEM) != 0) {
+                    got = ~0ull;
+                } else if (p.max_chunks) {
+                    // the budget is spent only on a queue that still has roots,
+                    // so a call makes progress while any root is left: a
+                    // budget holder's claim fails only when another holder
+                    // took the last chunk
+                    const unsigned long long h =
+                        __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (h >= (unsigned long long)(qend - qbeg)) got = h;
+                    else if (atomicAdd(&p.queues[kBudgetSlot * kQueueStride], 1ull) >= p.max_chunks)
+                        got = ~0ull;
+                    else got = atomicAdd(head, (unsigned long long)p.chunk);
+                } else {
+                    got = atomicAdd(head, (unsigned long long)p.chunk);
+                }
+            }
+            got = lane0_u64(got);
+            if (got == ~0ull) { stopped = true; break; }
+            if (got >= (unsigned long long)(qend - qbeg)) break;
+            const uint32_t base = uniform(qbeg + (uint32_t)got);
+            if (p.skip && p.skip[base / kWave]) continue;   // searched as an item
+            process_roots<TT, D, MODE>(p, W, cnt, lane, base, min(base + p.chunk, qend), st);
+        }
+    }
+
+    if constexpr (STATS) {
+#pragma unroll
+        for (int i = 0; i < kStats; ++i)
+            if (st.v[i]) atomicAdd(&p.stats[i], (unsigned long long)st.v[i]);
+    }
+    __syncthreads();
+    for (int i = (int)threadIdx.x; i < n_slots; i += (int)blockDim.x)
+        if (cnt[i]) atomicAdd(&p.counts[i], cnt[i]);
+}
+
+// Many (graph, tree) jobs in one persistent launch.  Waves claim work items
+// (root ranges of one job) from one queue; each wave keeps its own LDS
+// counters, sized for the largest tree, and flushes them after every item.
+template <typename TT, int D, int MODE>
+__global__ void __launch_bounds__(kWave * kWavesPerBlock)
+batch_kernel(const BatchParams<TT> bp) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const int wave = (int)(threadIdx.x / kWave);
+    const size_t cnt_bytes = ((size_t)bp.n_q_max * 8 + 15) & ~(size_t)15;
+    unsigned char *mine = smem + (size_t)wave * (cnt_bytes + sizeof(WaveLds<TT, D, false>));
+    unsigned long long *cnt = reinterpret_cast<unsigned long long *>(mine);
+    WaveLds<TT, D, false> &W = *reinterpret_cast<WaveLds<TT, D, false> *>(mine + cnt_bytes);
+    W.flag[lane] = 0;
+    Stats st;
+    for (;;) {
+        unsigned long long it = 0;
+        if (lane == 0) it = atomicAdd(bp.cursor, 1ull);
+        it = lane0_u64(it);
+        if (it >= bp.n_items) break;
+        const BatchItem item = bp.items[uniform((uint32_t)it)];
+        const BatchJob<TT> &job = bp.jobs[uniform(item.job)];
+        // the plain search keeps its own copy of the job's parameters (in
+        // registers); the multi-window one reads them in place, since its
+        // window selection would otherwise put a copy in scratch memory
+        auto search = [&](const KParams<TT> &p) {
+            const uint32_t ip = uniform(item.part);
+            if (ip & kItemSplit)
+                process_root_part<TT, D, MODE>(p, W, cnt, lane, uniform(item.begin),
+                                               (ip >> 15) & 0x7fffu, ip & 0x7fffu, st);
+            else
+                process_roots<TT, D, MODE>(p, W, cnt, lane, uniform(item.begin), uniform(item.end),
+                                           st);
+        };
+        const uint32_t nq = (uint32_t)counter_slots(job.p.tree);
+        for (uint32_t i = (uint32_t)lane; i < nq; i += kWave) cnt[i] = 0;
+        wave_sync();
+        if constexpr (MODE == 0) {
+            const KParams<TT> p = job.p;
+            search(p);
+        } else {
+            search(job.p);
+        }
+        wave_sync();
+        for (uint32_t i = (uint32_t)lane; i < nq; i += kWave)
+            if (cnt[i]) atomicAdd(&bp.counts[job.count_off + i], cnt[i]);
+        wave_sync();
+    }
+}
+
+
+template <typename TT, int D, int MODE>
+size_t smem_bytes(int n_q) {
+    return (((size_t)n_q * 8 + 15) & ~(size_t)15) +
+           (size_t)kWavesPerBlock * sizeof(WaveLds<TT, D, MODE == 2>);
+}
+
+template <typename TT, int D, int MODE>
+hipError_t launch_ds(const KParams<TT> &p, int blocks, hipStream_t stream) {
+    const size_t sm = smem_bytes<TT, D, MODE>(counter_slots(p.tree));
+    auto kern = comine_kernel<TT, D, MODE>;
+    if (sm > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+        if (e != hipSuccess) return e;
+    }
+    if (blocks <= 0) {
+        int dev = 0, ncu = 0, per = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kWave * kWavesPerBlock, sm);
+        if (e != hipSuccess) return e;
+        blocks = ncu * (per > 0 ? per : 1);
+    }
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kWave * kWavesPerBlock), sm, stream, p);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename TT, int D>
+hipError_t launch_d(const KParams<TT> &p, int blocks, hipStream_t stream) {
+    if (p.stats) return launch_ds<TT, D, 1>(p, blocks, stream);
+    if (p.root_cost) return launch_ds<TT, D, 2>(p, blocks, stream);
+    if (p.tree.n_d > 1) return launch_ds<TT, D, 3>(p, blocks, stream);
+    return launch_ds<TT, D, 0>(p, blocks, stream);
+}
+
+template <typename TT, int D, int MODE>
+hipError_t launch_batch_d(const BatchParams<TT> &bp, int blocks, hipStream_t stream) {
+    const size_t sm = (size_t)kWavesPerBlock *
+                      ((((size_t)bp.n_q_max * 8 + 15) & ~(size_t)15) + sizeof(WaveLds<TT, D, false>));
+    auto kern = batch_kernel<TT, D, MODE>;
+    if (sm > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+        if (e != hipSuccess) return e;
+    }
+    if (blocks <= 0) {
+        int dev = 0, ncu = 0, per = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kWave * kWavesPerBlock, sm);
+        if (e != hipSuccess) return e;
+        blocks = ncu * (per > 0 ? per : 1);
+    }
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kWave * kWavesPerBlock), sm, stream, bp);
+    return hipGetLastError();
+}
+
+}  // namespace mg

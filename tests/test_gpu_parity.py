@@ -154,6 +154,32 @@ def test_multi_window_medium_every_path():
     assert np.array_equal(api.count_noalloc(g, tr), want)
 
 
+def test_autotuner_and_its_cache(tmp_path):
+    """mg_tune picks settings by timing, appends them to its cache and reads
+    them back without timing; counts with the tuned settings equal the
+    oracle's."""
+    s, d, t, n, ms = _medium(seed=4, E=30000, V=200, tmax=20000)
+    og = OracleGraph(s, d, t, n)
+    want = oracle_counts(og, ms, 300)
+    g = api.Graph(s, d, t, n)
+    tr = api.Tree(ms, 300)
+    cache = str(tmp_path / "tune.jsonl")
+    say("tune")
+    r = api.tune(g, tr, cache=cache)
+    assert r["from_cache"] == 0 and r["trials"] >= 10 and r["ms"] <= r["default_ms"]
+    assert r["chunk"] % 64 == 0 and 1 <= r["queues"] <= 8 and r["leaf_scan"] > 0
+    r2 = api.tune(g, tr, cache=cache)
+    assert r2["from_cache"] == 1 and r2["trials"] == 0
+    assert {k: r2[k] for k in ("blocks", "chunk", "queues", "leaf_scan")} == \
+        {k: r[k] for k in ("blocks", "chunk", "queues", "leaf_scan")}
+    assert len(open(cache).read().splitlines()) == 1
+    kw = {k: r[k] for k in ("blocks", "chunk", "queues", "leaf_scan")}
+    assert np.array_equal(api.count(g, tr, **kw), want)
+    # another tree is another key
+    r3 = api.tune(g, api.Tree(ms[:5], 300), cache=cache)
+    assert r3["from_cache"] == 0 and len(open(cache).read().splitlines()) == 2
+
+
 def test_stop_and_resume():
     """A count stopped by a chunk budget and resumed from its cursor until
     done sums to the oracle's counts and statistics, on every root and on a
