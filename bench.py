@@ -110,7 +110,49 @@ def cpu_baseline(s, d, t, n, motifs, delta, target_s):
     og.close()
     return {"value": n_s / dt, "unit": "root edges/s", "cores": threads, "kind": "oracle",
             "sample": "%d consecutive roots from the middle of the time order, all %d motifs, "
-                      "one oracle pass per motif (%.1f s)" % (n_s, len(motifs), dt)}
+                      "one oracle pass per motif (%.1f s)" % (n_s, len(motifs), dt)}, roots
+
+
+def cpu_backend(api, s, d, t, n, motifs, delta, roots, threads):
+    """The library's CPU backend (generated nested loops per trie level) on
+    the oracle's sample: co-mining and per-motif mining, both timed without
+    code generation (the paper's CPU co-mining speed-up, measured here)."""
+    import numpy as np
+    import oracle
+    g = api.Graph(s, d, t, n, sorted_by_t=True, host_only=True)
+    tr = api.Tree(motifs, delta)
+    c, ms = api.count_cpu(g, tr, roots=roots, threads=threads, timed=True)
+    pm, ms_pm = api.count_cpu(g, tr, roots=roots, threads=threads, mode="per_motif", timed=True)
+    og = oracle.OracleGraph(s, d, t, n)
+    head = roots[: min(len(roots), 200000)]
+    want = np.array([og.count(m, delta, roots=head) for m in motifs], np.uint64)
+    og.close()
+    ok = bool(np.array_equal(api.count_cpu(g, tr, roots=head, threads=threads), want)
+              and np.array_equal(pm, c))
+    if not ok:
+        raise SystemExit("CPU backend counts differ from the oracle")
+    return {"comine_root_edges_per_s": len(roots) / (ms / 1e3),
+            "per_motif_root_edges_per_s": len(roots) / (ms_pm / 1e3),
+            "comine_speedup_vs_per_motif": ms_pm / ms, "threads": threads,
+            "sample": "the oracle's sample (%d roots)" % len(roots)}
+
+
+def idle_tail(api, g, tr, **kw):
+    """How evenly the waves of one count finish: every wave's start and end
+    (device real-time clock).  idle_frac = 1 - (sum of wave busy times) /
+    (waves x launch span): the share of the launch the waves spend done or
+    not yet started, the most that any reordering of the same work can save."""
+    import numpy as np
+    clk = np.zeros(2 * 256 * 64, dtype=np.uint64)
+    api.count(g, tr, wave_clock=clk, **kw)
+    st, en = clk[0::2].astype(np.int64), clk[1::2].astype(np.int64)
+    live = en > 0
+    st, en = st[live], en[live]
+    span = float(en.max() - st.min())
+    busy = float((en - st).sum())
+    return {"waves": int(live.sum()), "idle_frac": 1.0 - busy / (len(st) * span),
+            "last_wave_tail_frac": float(en.max() - np.median(en)) / span,
+            "start_spread_frac": float(st.max() - st.min()) / span}
 
 
 def timed_steps(fn, steps, warmup):
@@ -240,6 +282,8 @@ def bench_learned(args):
     tp_, _ = timed_steps(lambda: api.count(g, tr), args.steps, args.warmup)
     tl_, c = timed_steps(lambda: api.count(g, tr, model=model), args.steps, args.warmup)
     assert np.array_equal(c, ref)
+    balance = {"plain": idle_tail(api, g, tr), "learned": idle_tail(api, g, tr, model=model)}
+    log("wave balance", balance)
     out = {
         "metric": "root edges searched/s, learned schedule (config 4), exact counts",
         "value": E / tl_, "unit": "root edges/s", "n_gpus": 1, "steps": args.steps,
@@ -248,7 +292,7 @@ def bench_learned(args):
         "data": "synthetic",
         "config": {"workload": "powerlaw V=%d E=%d gamma=1.8 delta=%d, 756 motifs "
                                "(3- and 4-edge, <=4 nodes)" % (n, E, delta)},
-        "plain_ms": 1e3 * tp_, "speedup_vs_plain": tp_ / tl_,
+        "plain_ms": 1e3 * tp_, "speedup_vs_plain": tp_ / tl_, "wave_balance": balance,
         "held_out_spearman": rho, "train_loss": [float(x) for x in loss], "train_s": train_s,
     }
     if args.per_motif_steps:
@@ -299,6 +343,8 @@ def bench_sweep(args):
     assert np.array_equal(np.stack(out), ref)
     t1, out = timed_steps(lambda: api.count(g, tm), args.steps, args.warmup)
     assert np.array_equal(out, ref)
+    balance = idle_tail(api, g, tm)
+    log("wave balance", balance)
     # model trained on a separately seeded graph of the same recipe, a tenth of the size
     V2, E2 = max(16, n // 10), max(16, E // 10)
     s2, d2, t2 = W.powerlaw_graph(V2, E2, 2.0, 100_000_000, seed=105, burst_cap=32)
@@ -325,6 +371,7 @@ def bench_sweep(args):
         "config": {"workload": "powerlaw V=%d E=%d gamma=2.0 span=1e8 s, 48 motifs of 3-5 "
                                "edges, windows %s" % (n, E, windows)},
         "three_searches_ms": 1e3 * t3, "speedup_vs_three_searches": t3 / t1,
+        "wave_balance": balance,
         "learned_batched_ms": 1e3 * (tl + predict_s), "learned_batched_step_ms": 1e3 * tl,
         "learned_predict_ms": 1e3 * predict_s, "speedup_learned_vs_plain": t1 / (tl + predict_s),
         "train_loss": [float(x) for x in loss], "counts_total": [int(r.sum()) for r in ref],
@@ -447,6 +494,8 @@ def main():
         log("per-motif: %.3f ms/step wall, kernels %.3f ms"
             % (1e3 * pm_step, sum(pm_ms) / len(pm_ms)))
 
+    balance = idle_tail(api, g, tr, **kw)
+    log("wave balance", balance)
     k_avg_s = sum(kms) / len(kms) / 1e3
     achieved = algo_bytes / k_avg_s / 1e9
     rec = counter_record(E)
@@ -494,11 +543,15 @@ def main():
         "roofline": roofline,
         "stats": st,
         "tuning": tuning,
+        "wave_balance": balance,
         "total_matches": int(counts.sum()),
     }
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
-        out["cpu_baseline"] = cpu_baseline(s, d, t, n, motifs, delta, args.cpu_seconds)
+        out["cpu_baseline"], roots = cpu_baseline(s, d, t, n, motifs, delta, args.cpu_seconds)
+        log("cpu backend ...")
+        out["cpu_backend"] = cpu_backend(api, s, d, t, n, motifs, delta, roots,
+                                         out["cpu_baseline"]["cores"])
     print(json.dumps(out), flush=True)
 
 

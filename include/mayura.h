@@ -50,6 +50,9 @@ typedef enum {
 #define MG_SORTED_BY_T 1u          /* caller promises t is non-decreasing */
 #define MG_DEVICE_INPUT 2u         /* src, dst and t are device pointers (current
                                       device); they are read on `stream` */
+#define MG_HOST_ONLY 4u            /* keep the graph on the host only, for the CPU
+                                      backend (mg_count_cpu); no device is needed and
+                                      the GPU entry points refuse the graph */
 
 typedef struct mg_graph mg_graph;  /* opaque */
 typedef struct mg_tree mg_tree;    /* opaque */
@@ -143,6 +146,9 @@ void mg_tree_destroy(mg_tree *tr);
 /* count modes */
 #define MG_MODE_COMINE 0      /* one search over the whole MG-Tree (Algorithm 3) */
 #define MG_MODE_PER_MOTIF 1   /* one search per distinct motif (Algorithm 1 per motif) */
+#define MG_MODE_AUTO 2        /* mg_count only: co-mining or per-motif mining as the
+                                 paper's heuristic advises for the GPU
+                                 (mg_comine_advice) */
 
 typedef struct {
     int32_t mode;             /* MG_MODE_* */
@@ -187,6 +193,14 @@ typedef struct {
                                  in this call (and at least one while roots are
                                  left, unless stopped by the flag) */
     struct mg_cursor *cursor; /* NULL, or in/out resume point (below) */
+    uint64_t *wave_clock;     /* optional out (co-mining only), wave_clock_len
+                                 entries: entries 2w and 2w + 1 get the start and
+                                 end of wave w's search in ticks of the device's
+                                 constant real-time clock (its rate is
+                                 hipDeviceAttributeWallClockRate, kHz); entries of
+                                 waves not launched are 0.  For measuring how
+                                 evenly a schedule ends; counts are unchanged. */
+    int64_t wave_clock_len;
 } mg_count_opts;
 
 /* Resume point of a stopped count.  Initialise with mg_cursor_init; pass the
@@ -239,6 +253,28 @@ int mg_count(const mg_graph *g, const mg_tree *tr, const mg_count_opts *opts,
              uint64_t *counts);
 
 /*
+ * Enumeration: every match itself, not only the counts (paper, section 2.1:
+ * a match is a sequence of edges; the matcher of Algorithm 1 records each one
+ * it completes).  The count sizes the output, then the same search writes one
+ * record per match -- the motif and its edges in the motif's order -- in no
+ * particular order.
+ *   out       : host, capacity records; with NULL or a capacity below the
+ *               number of matches nothing is written and *n_matches tells how
+ *               many records are needed
+ *   motif     : the caller's motif index (for duplicate motifs, the first one
+ *               with that edge sequence; the others have the same matches)
+ *   edges     : the caller's edge indices (the input order of
+ *               mg_graph_create), -1 past the motif's length
+ * MG_EUNSUPPORTED for a tree with several windows.
+ */
+typedef struct {
+    int32_t motif;
+    int32_t edges[MG_MAX_EDGES_PER_MOTIF];
+} mg_match;
+int mg_enumerate(const mg_graph *g, const mg_tree *tr, void *stream, mg_match *out,
+                 int64_t capacity, int64_t *n_matches);
+
+/*
  * mg_count for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
  * same search, with its queue heads, counters and statistics in a static
@@ -248,7 +284,7 @@ int mg_count(const mg_graph *g, const mg_tree *tr, const mg_count_opts *opts,
  *   opts : NULL = defaults.  Accepted: blocks, chunk, queues, stream,
  *          leaf_scan, stats, stop, max_chunks.  MG_EINVAL for anything that
  *          needs memory of its own: per-motif mode, the learned schedule,
- *          roots, root_cost, elapsed_ms, cursor.
+ *          roots, root_cost, elapsed_ms, cursor, wave_clock.
  * The tree's device tables must already exist on the current device (any
  * earlier mg_count of the tree there creates them), else MG_EINVAL.
  * MG_EUNSUPPORTED when the tree has more distinct motifs than the array
@@ -260,6 +296,47 @@ int mg_count(const mg_graph *g, const mg_tree *tr, const mg_count_opts *opts,
 #define MG_NOALLOC_SCRATCH_BYTES ((160 + MG_MAX_QUERIES + 8) * 8)   /* 34,112 */
 int mg_count_noalloc(const mg_graph *g, const mg_tree *tr, const mg_count_opts *opts,
                      uint64_t *counts);
+
+/*
+ * CPU backend (paper, section 5.1.1 "CPU code-generation" and its appendix
+ * listing of the generated nested loops): the search of the tree is emitted
+ * as C++ with one loop nest per level of the prefix trie, compiled by the
+ * host compiler (MG_CXX, else c++; once per tree), loaded and run over the
+ * root edges on the host's cores with dynamic chunks of roots.  codegen = 0
+ * interprets the trie instead (the recursion of the paper's CPU baseline).
+ * The graph may be MG_HOST_ONLY; a device graph is read back once.  Counts
+ * as mg_count (exact, every window of the tree).
+ */
+typedef struct {
+    int32_t mode;             /* MG_MODE_COMINE or MG_MODE_PER_MOTIF */
+    int32_t threads;          /* 0 = every host core */
+    int32_t codegen;          /* 1 = generated and compiled search (default), 0 = interpreted */
+    int32_t reserved;
+    const int64_t *roots;     /* host: root positions; NULL = all */
+    int64_t n_roots;
+    double *elapsed_ms;       /* optional out: wall time of the searches (code
+                                 generation and compilation not included) */
+} mg_cpu_opts;
+void mg_cpu_opts_init(mg_cpu_opts *opts);
+int mg_count_cpu(const mg_graph *g, const mg_tree *tr, const mg_cpu_opts *opts,
+                 uint64_t *counts);
+
+/*
+ * The paper's heuristic for whether co-mining pays (section 7, "Heuristic
+ * for Co-Mining"): on a bipartite graph (edges taken as undirected) always;
+ * on the GPU not when the group's similarity SM is below 0.44 (the paper's
+ * measured break-even); otherwise yes (a smaller window helps further).
+ */
+#define MG_PLATFORM_GPU 0
+#define MG_PLATFORM_CPU 1
+#define MG_GPU_SM_THRESHOLD 0.44
+typedef struct {
+    int32_t co_mine;          /* 1 = co-mine, 0 = mine each motif on its own */
+    int32_t bipartite;        /* the graph is bipartite */
+    double similarity;        /* the tree's SM */
+    double threshold;         /* the SM the platform needs (0 on the CPU) */
+} mg_advice;
+int mg_comine_advice(const mg_graph *g, const mg_tree *tr, int32_t platform, mg_advice *out);
 
 /*
  * Autotuner (not in the paper): picks the launch settings of mg_count for a

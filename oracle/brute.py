@@ -90,3 +90,16 @@ def window_entries(src, dst, t, motif, delta):
                     lst = E
                 out[r][j] += sum(1 for e in lst if t_prev < e[2] <= t_first + delta)
     return out
+
+
+def matches(src, dst, t, motif, delta):
+    """Every match as a tuple of the caller's edge indices (the motif's edges
+    in order), sorted: the definition applied to every k-subset of edges, as
+    count does, with the edges listed instead of counted."""
+    order = sorted(range(len(t)), key=lambda i: (int(t[i]), i))
+    E = [(int(src[i]), int(dst[i]), int(t[i])) for i in order]
+    out = []
+    for comb in itertools.combinations(range(len(E)), len(motif)):
+        if is_match([E[i] for i in comb], motif, delta):
+            out.append(tuple(order[i] for i in comb))
+    return sorted(out)

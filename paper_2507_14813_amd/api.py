@@ -22,6 +22,7 @@ MODE_COMINE = 0
 MODE_PER_MOTIF = 1
 SORTED_BY_T = 1
 DEVICE_INPUT = 2
+HOST_ONLY = 4
 
 _STATUS = {0: "MG_OK", -1: "MG_EINVAL", -2: "MG_ENOMEM", -3: "MG_EDEVICE",
            -4: "MG_EUNSUPPORTED", -5: "MG_EINTERNAL"}
@@ -58,7 +59,8 @@ class CountOpts(ctypes.Structure):
                 ("leaf_scan", ctypes.c_int32), ("model", ctypes.c_void_p),
                 ("root_cost", ctypes.c_void_p), ("sample", ctypes.c_int32),
                 ("stop", ctypes.c_void_p), ("max_chunks", ctypes.c_int64),
-                ("cursor", ctypes.c_void_p)]
+                ("cursor", ctypes.c_void_p), ("wave_clock", ctypes.c_void_p),
+                ("wave_clock_len", ctypes.c_int64)]
 
 
 class TuneResult(ctypes.Structure):
@@ -66,6 +68,18 @@ class TuneResult(ctypes.Structure):
                 ("queues", ctypes.c_int32), ("leaf_scan", ctypes.c_int32),
                 ("ms", ctypes.c_float), ("default_ms", ctypes.c_float),
                 ("from_cache", ctypes.c_int32), ("trials", ctypes.c_int32)]
+
+
+class CpuOpts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("threads", ctypes.c_int32),
+                ("codegen", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("roots", ctypes.c_void_p), ("n_roots", ctypes.c_int64),
+                ("elapsed_ms", ctypes.POINTER(ctypes.c_double))]
+
+
+class Advice(ctypes.Structure):
+    _fields_ = [("co_mine", ctypes.c_int32), ("bipartite", ctypes.c_int32),
+                ("similarity", ctypes.c_double), ("threshold", ctypes.c_double)]
 
 
 class Cursor(ctypes.Structure):
@@ -146,6 +160,11 @@ def lib():
         L.mg_cursor_init.restype = None
         L.mg_count_noalloc.argtypes = [p, p, ctypes.POINTER(CountOpts), p]
         L.mg_tune.argtypes = [p, p, ctypes.c_char_p, p, ctypes.POINTER(TuneResult)]
+        L.mg_enumerate.argtypes = [p, p, p, p, i64, ctypes.POINTER(i64)]
+        L.mg_cpu_opts_init.argtypes = [ctypes.POINTER(CpuOpts)]
+        L.mg_cpu_opts_init.restype = None
+        L.mg_count_cpu.argtypes = [p, p, ctypes.POINTER(CpuOpts), p]
+        L.mg_comine_advice.argtypes = [p, p, i32, ctypes.POINTER(Advice)]
         L.mg_last_error.restype = ctypes.c_char_p
         L.mg_model_create.argtypes = [ctypes.c_uint64, ctypes.POINTER(p)]
         L.mg_model_get_weights.argtypes = [p, p]
@@ -165,7 +184,8 @@ def lib():
         L.mg_batch_destroy.restype = None
         L.mg_count_batch.argtypes = [p, p, i32, ctypes.POINTER(BatchOpts), p]
         for f in ("mg_set_allocator", "mg_graph_create", "mg_graph_info",
-                  "mg_tree_create", "mg_tree_create_multi", "mg_tree_info", "mg_count", "mg_count_noalloc", "mg_tune", "mg_batch_create",
+                  "mg_tree_create", "mg_tree_create_multi", "mg_tree_info", "mg_count", "mg_count_noalloc", "mg_tune", "mg_enumerate", "mg_count_cpu",
+                  "mg_comine_advice", "mg_batch_create",
                   "mg_batch_count", "mg_batch_info", "mg_count_batch", "mg_model_create", "mg_model_get_weights",
                   "mg_model_set_weights", "mg_model_get_moments", "mg_root_features", "mg_model_predict",
                   "mg_model_train"):
@@ -223,11 +243,11 @@ class Graph:
     """A temporal graph resident on the current GPU (``mg_graph_create``)."""
 
     def __init__(self, src, dst, t, n_nodes, sorted_by_t=False, stream=None,
-                 torch_allocator=True):
+                 torch_allocator=True, host_only=False):
         L = lib()
-        if torch_allocator:
+        if torch_allocator and not host_only:
             use_torch_allocator()
-        flags = SORTED_BY_T if sorted_by_t else 0
+        flags = (SORTED_BY_T if sorted_by_t else 0) | (HOST_ONLY if host_only else 0)
         if all(hasattr(x, "is_cuda") and x.is_cuda for x in (src, dst, t)):
             # torch tensors on the GPU: handed over as device pointers
             import torch
@@ -316,7 +336,7 @@ class Tree:
 
 def count(graph: Graph, tree: Tree, mode="comine", roots=None, blocks=0, chunk=0,
           queues=0, stream=None, timed=False, stats=False, root_cost=False, model=None,
-          leaf_scan=0, sample=0, stop=None, max_chunks=0, cursor=None):
+          leaf_scan=0, sample=0, stop=None, max_chunks=0, cursor=None, wave_clock=None):
     """Exact count per motif (``mg_count``), in the tree's motif order.
 
     ``mode``: "comine" (one search over the MG-Tree) or "per_motif" (one search
@@ -329,11 +349,13 @@ def count(graph: Graph, tree: Tree, mode="comine", roots=None, blocks=0, chunk=0
     ``stop`` (address of an int32 flag in pinned host or device memory),
     ``max_chunks`` and ``cursor`` (a ``Cursor``, updated in place) stop a
     count early and resume it; the counts are then those of this call.
+    ``wave_clock`` (a uint64 array, filled in place) receives every wave's
+    start and end ticks.
     """
     L = lib()
     o = CountOpts()
     L.mg_count_opts_init(ctypes.byref(o))
-    o.mode = {"comine": MODE_COMINE, "per_motif": MODE_PER_MOTIF}[mode]
+    o.mode = {"comine": MODE_COMINE, "per_motif": MODE_PER_MOTIF, "auto": 2}[mode]
     o.blocks = int(blocks)
     o.chunk = int(chunk)
     o.queues = int(queues)
@@ -348,6 +370,10 @@ def count(graph: Graph, tree: Tree, mode="comine", roots=None, blocks=0, chunk=0
     o.max_chunks = int(max_chunks)
     if cursor is not None:
         o.cursor = ctypes.addressof(cursor)
+    if wave_clock is not None:
+        assert wave_clock.dtype == np.uint64 and wave_clock.flags.c_contiguous
+        o.wave_clock = wave_clock.ctypes.data
+        o.wave_clock_len = wave_clock.size
     r = None
     if roots is not None:
         r = np.ascontiguousarray(roots, dtype=np.int64)
@@ -373,6 +399,53 @@ def count(graph: Graph, tree: Tree, mode="comine", roots=None, blocks=0, chunk=0
     if root_cost:
         res.append(rcost[:graph.n_edges])
     return res[0] if len(res) == 1 else tuple(res)
+
+
+def count_cpu(graph: Graph, tree: Tree, mode="comine", threads=0, codegen=True, roots=None,
+              timed=False):
+    """``mg_count_cpu``: the CPU backend (generated and compiled nested loops
+    per trie level, or the interpreted trie with ``codegen=False``).  Counts
+    as ``count``; with ``timed`` also the wall milliseconds of the search."""
+    L = lib()
+    o = CpuOpts()
+    L.mg_cpu_opts_init(ctypes.byref(o))
+    o.mode = {"comine": MODE_COMINE, "per_motif": MODE_PER_MOTIF}[mode]
+    o.threads = int(threads)
+    o.codegen = 1 if codegen else 0
+    r = None
+    if roots is not None:
+        r = np.ascontiguousarray(roots, dtype=np.int64)
+        o.roots = r.ctypes.data if r.size else _p(np.zeros(1, np.int64)).value
+        o.n_roots = r.size
+    ms = ctypes.c_double(0.0)
+    if timed:
+        o.elapsed_ms = ctypes.pointer(ms)
+    out = np.zeros(tree.n_motifs * tree.n_deltas, dtype=np.uint64)
+    _check(L.mg_count_cpu(graph.handle, tree.handle, ctypes.byref(o), _p(out)))
+    out = tree.shape_counts(out)
+    return (out, float(ms.value)) if timed else out
+
+
+def comine_advice(graph: Graph, tree: Tree, platform="gpu"):
+    """``mg_comine_advice``: the paper's heuristic for whether co-mining pays."""
+    a = Advice()
+    _check(lib().mg_comine_advice(graph.handle, tree.handle,
+                                  {"gpu": 0, "cpu": 1}[platform], ctypes.byref(a)))
+    return {f: getattr(a, f) for f, _ in Advice._fields_}
+
+
+def enumerate_matches(graph: Graph, tree: Tree, stream=None):
+    """``mg_enumerate``: every match, as (motif index array, edges array of
+    shape n x 5 with -1 past each motif's length), in no particular order;
+    edges are indices into the arrays the graph was created from."""
+    L = lib()
+    n = ctypes.c_int64(0)
+    st = _default_stream(stream)
+    _check(L.mg_enumerate(graph.handle, tree.handle, st, None, 0, ctypes.byref(n)))
+    rec = np.zeros((max(1, n.value), 6), dtype=np.int32)
+    _check(L.mg_enumerate(graph.handle, tree.handle, st, _p(rec), n.value, ctypes.byref(n)))
+    rec = rec[:n.value]
+    return rec[:, 0].copy(), rec[:, 1:].copy()
 
 
 def tune(graph: Graph, tree: Tree, cache=None, stream=None):

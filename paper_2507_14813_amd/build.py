@@ -50,7 +50,7 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
     depths in separate files) and link libmayura.so."""
     from concurrent.futures import ThreadPoolExecutor
     os.makedirs(BUILD_DIR, exist_ok=True)
-    names = list(HIP_SOURCES) + ["host.cpp"]
+    names = list(HIP_SOURCES) + ["host.cpp", "cpu.cpp"]
     jobs = jobs or min(len(names), max(1, os.cpu_count() or 1))
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         results = list(ex.map(_compile, names))
@@ -60,7 +60,7 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
             print(out)
         objs.append(obj)
     tmp = OUT + ".tmp%d" % os.getpid()
-    _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", tmp])
+    _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-ldl", "-lpthread", "-o", tmp])
     os.replace(tmp, OUT)
     return OUT
 

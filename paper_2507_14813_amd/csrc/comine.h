@@ -115,6 +115,15 @@ struct KParams {
     const uint32_t *n_items;      // device count of items (with items)
     const uint8_t *skip;          // NULL, or per 64-root segment: 1 = covered by the
                                   // items (needs 64-root chunks and roots NULL)
+    int32_t *enum_out;            // NULL, or enumeration: records of 1 + kKMax words
+                                  // (distinct motif, edge ids, -1 past the motif's
+                                  // length), enum_cap of them, at slots taken from
+                                  // *enum_cursor (zeroed); needs leaf_scan 0
+    unsigned long long *enum_cursor;
+    unsigned long long enum_cap;
+    unsigned long long *wave_clock;  // NULL, or per wave: start and end of its search
+                                     // (device real-time clock ticks)
+    uint32_t n_wave_clock;           // waves that wave_clock holds
     uint32_t leaf_scan;           // windows whose children are all leaves are counted
                                   // without the candidate expansion: by one lane up
                                   // to this long, by the whole wave when longer

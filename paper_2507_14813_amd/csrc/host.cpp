@@ -19,6 +19,7 @@
 
 #include "../../include/mayura.h"
 #include "comine.h"
+#include "handles.h"
 #include "sched.h"
 
 using mg::kVMax;
@@ -34,7 +35,7 @@ static_assert(MG_MAX_QUERIES == mg::kMaxQueries, "query limit");
 static_assert(MG_MAX_DELTAS == mg::kMaxDeltas, "window limit");
 static_assert(MG_NOALLOC_SCRATCH_BYTES == 8 * mg::kStaticWords, "static scratch size");
 
-namespace {
+namespace mgh {
 
 thread_local std::string g_err;
 
@@ -59,15 +60,6 @@ int fail(int code, const char *fmt, ...) {
 mg_alloc_fn g_alloc = nullptr;
 mg_release_fn g_release = nullptr;
 void *g_alloc_ctx = nullptr;
-
-struct DevBuf {
-    void *ptr = nullptr;
-    size_t bytes = 0;
-    void *stream = nullptr;
-    bool custom = false;
-    mg_release_fn release = nullptr;
-    void *ctx = nullptr;
-};
 
 int dev_alloc(DevBuf &b, size_t bytes, void *stream) {
     b.bytes = bytes;
@@ -99,24 +91,15 @@ void dev_free(DevBuf &b) {
     b.ptr = nullptr;
 }
 
-}  // namespace
+}  // namespace mgh
 
-// ---------------------------------------------------------------- graph
-struct mg_graph {
-    int64_t E = 0;
-    int32_t V = 0;
-    int64_t self_loops = 0;
-    int64_t t_min = 0, t_max = 0;
-    int time_bytes = 4;
-    int device = 0;
-    DevBuf gsrc, gdst, gt, gx, out_eid, in_eid, out_off, out_adj, in_off, in_adj;
-    int64_t device_bytes = 0;
-    ~mg_graph() {
-        for (DevBuf *b : {&gsrc, &gdst, &gt, &gx, &out_eid, &in_eid, &out_off, &out_adj, &in_off,
-                          &in_adj})
-            dev_free(*b);
-    }
-};
+using namespace mgh;
+
+mg_graph::~mg_graph() {
+    for (DevBuf *b : {&gsrc, &gdst, &gt, &gx, &out_eid, &in_eid, &out_off, &out_adj, &in_off,
+                      &in_adj})
+        dev_free(*b);
+}
 
 namespace {
 
@@ -210,40 +193,11 @@ int upload_graph(mg_graph *g, const std::vector<int32_t> &s, const std::vector<i
 }  // namespace
 
 // ---------------------------------------------------------------- tree
-namespace {
-
-struct TrieNode {
-    int parent = -1;
-    int u = 0, v = 0;      // edge that extends the parent (canonical labels)
-    int depth = 0;         // edges in the prefix
-    int nv = 0;            // vertices bound after the prefix
-    std::vector<int> kids;
-    int q = -1;            // distinct motif whose edge sequence is this prefix
-};
-
-using Motif = std::vector<std::pair<int, int>>;
-
-}  // namespace
-
-struct mg_tree {
-    int32_t n_motifs = 0;
-    int64_t delta = 0;                  // the largest window
-    std::vector<int64_t> deltas;        // distinct windows, ascending
-    std::vector<int32_t> delta_slot;    // caller's window i -> index in deltas
-    std::vector<int32_t> motif_q;       // caller motif -> distinct id
-    std::vector<Motif> distinct;
-    std::vector<TrieNode> nodes;        // node 0 = prefix ((0,1))
-    std::vector<int32_t> node_tab;      // one word per internal node
-    std::vector<int32_t> grp_tab;       // 8 words per group
-    int32_t depth = 0, root_q = -1;
-    mg_tree_info_t info{};
-    // device copies
-    int device = -1;
-    DevBuf d_node, d_grp;
-    // per-motif chain trees (built on first per-motif count)
-    std::vector<std::unique_ptr<mg_tree>> singles;
-    ~mg_tree() { dev_free(d_node); dev_free(d_grp); }
-};
+mg_tree::~mg_tree() {
+    dev_free(d_node);
+    dev_free(d_grp);
+    release_cpu_code(this);
+}
 
 namespace {
 
@@ -507,11 +461,13 @@ template <typename TT>
 int launch_tree(const mg_graph *g, mg_tree *tr, const uint32_t *d_roots, uint32_t n_roots,
                 unsigned long long *d_queues, unsigned long long *d_counts,
                 unsigned long long *d_stats, unsigned long long *d_cost,
-                const mg_count_opts &o, hipStream_t st, float *ms) {
+                unsigned long long *d_clock, const mg_count_opts &o, hipStream_t st, float *ms) {
     mg::KParams<TT> p{};
     fill_params<TT>(p, g, tr, o, d_queues, d_counts, d_stats, d_cost);
     p.roots = d_roots;
     p.n_roots = n_roots;
+    p.wave_clock = d_clock;
+    p.n_wave_clock = d_clock ? (uint32_t)std::min<int64_t>(o.wave_clock_len / 2, 0x7fffffff) : 0u;
 
     if (o.cursor && o.cursor->started) {
         // resume: every root queue starts where the last call stopped
@@ -550,6 +506,18 @@ int launch_tree(const mg_graph *g, mg_tree *tr, const uint32_t *d_roots, uint32_
 }
 
 }  // namespace
+
+int mgh::chain_trees(mg_tree *tr) {
+    if (!tr->singles.empty()) return MG_OK;
+    for (const Motif &m : tr->distinct) {
+        mg_tree *one = nullptr;
+        int rc = make_tree({m}, tr->deltas, &one);
+        if (rc) return rc;
+        tr->singles.emplace_back(one);
+    }
+    return MG_OK;
+}
+
 
 // ---------------------------------------------------------------- cost model
 static_assert(mg::kParams == MG_MODEL_PARAMS, "parameter layout");
@@ -984,6 +952,7 @@ int mg_root_features(const mg_graph *g, const mg_tree *tr_c, const int64_t *root
                      float *feats) {
     try {
         if (!g || !tr_c || !feats || n < 0) return fail(MG_EINVAL, "bad argument");
+        if (g->host_only) return fail(MG_EINVAL, "the graph is on the host only (MG_HOST_ONLY)");
         if (!roots && n != g->E) return fail(MG_EINVAL, "without roots, n must be n_edges");
         mg_tree *tr = const_cast<mg_tree *>(tr_c);
         int rc = upload_tree(tr, g->device, nullptr);
@@ -1108,6 +1077,7 @@ int mg_batch_create(const mg_graph *const *graphs, const mg_tree *const *trees, 
         hipStream_t st = (hipStream_t)o.stream;
         for (int32_t j = 0; j < n; ++j) {
             if (!graphs[j] || !trees[j]) return fail(MG_EINVAL, "job %d has a NULL handle", j);
+            if (graphs[j]->host_only) return fail(MG_EINVAL, "job %d: graph on the host only", j);
             if (graphs[j]->device != dev) return fail(MG_EINVAL, "job %d: graph on another device", j);
             if (j && graphs[j]->time_bytes != graphs[0]->time_bytes)
                 return fail(MG_EUNSUPPORTED, "graphs of one batch must share the time width");
@@ -1242,7 +1212,10 @@ int mg_graph_create(const int32_t *src, const int32_t *dst, const int64_t *t, in
         if (n_edges >= (int64_t)1 << 31)
             return fail(MG_EUNSUPPORTED, "n_edges %lld >= 2^31", (long long)n_edges);
         if (n_nodes >= INT32_MAX) return fail(MG_EUNSUPPORTED, "n_nodes too large");
-        if (flags & ~(MG_SORTED_BY_T | MG_DEVICE_INPUT)) return fail(MG_EINVAL, "unknown flags");
+        if (flags & ~(MG_SORTED_BY_T | MG_DEVICE_INPUT | MG_HOST_ONLY))
+            return fail(MG_EINVAL, "unknown flags");
+        if ((flags & MG_DEVICE_INPUT) && (flags & MG_HOST_ONLY))
+            return fail(MG_EINVAL, "MG_DEVICE_INPUT and MG_HOST_ONLY exclude each other");
         std::vector<int32_t> hs, hd;
         std::vector<int64_t> ht;
         if ((flags & MG_DEVICE_INPUT) && n_edges > 0) {
@@ -1286,6 +1259,7 @@ int mg_graph_create(const int32_t *src, const int32_t *dst, const int64_t *t, in
             for (int64_t i = 0; i < n_edges; ++i) {
                 s[i] = src[ord[i]]; d[i] = dst[ord[i]]; tt[i] = t[ord[i]];
             }
+            g->input_index = std::move(ord);
         }
         for (int64_t i = 0; i < n_edges; ++i) g->self_loops += (s[i] == d[i]);
         g->t_min = n_edges ? tt[0] : 0;
@@ -1293,6 +1267,13 @@ int mg_graph_create(const int32_t *src, const int32_t *dst, const int64_t *t, in
         if (n_edges && g->t_max - g->t_min < 0) return fail(MG_EUNSUPPORTED, "time span >= 2^63");
         const uint64_t span = n_edges ? (uint64_t)(g->t_max - g->t_min) : 0;
         g->time_bytes = span < 0xffffffffull ? 4 : 8;
+        if (flags & MG_HOST_ONLY) {
+            g->host_only = true;
+            g->device = -1;
+            build_host(g.get(), std::move(s), std::move(d), std::move(tt));
+            *out = g.release();
+            return MG_OK;
+        }
         HIP_TRY(hipGetDevice(&g->device));
         hipStream_t st = (hipStream_t)stream;
         int rc = g->time_bytes == 4 ? upload_graph<uint32_t>(g.get(), s, d, tt, st)
@@ -1363,15 +1344,95 @@ int mg_tree_info(const mg_tree *tr, mg_tree_info_t *out) {
 
 void mg_tree_destroy(mg_tree *tr) { delete tr; }
 
+int mg_enumerate(const mg_graph *g, const mg_tree *tr_c, void *stream, mg_match *out,
+                 int64_t capacity, int64_t *n_matches) {
+    try {
+        if (!g || !tr_c || !n_matches || capacity < 0) return fail(MG_EINVAL, "bad argument");
+        if (g->host_only) return fail(MG_EINVAL, "the graph is on the host only (MG_HOST_ONLY)");
+        mg_tree *tr = const_cast<mg_tree *>(tr_c);
+        if (tr->deltas.size() != 1)
+            return fail(MG_EUNSUPPORTED, "enumeration takes a tree with one window");
+        static_assert(sizeof(mg_match) == 4 * (1 + mg::kKMax), "record layout");
+        // the count sizes the output
+        mg_count_opts o;
+        mg_count_opts_init(&o);
+        o.stream = stream;
+        std::vector<uint64_t> cnt(tr->n_motifs);
+        int rc = mg_count(g, tr, &o, cnt.data());
+        if (rc) return rc;
+        std::vector<int32_t> first(tr->distinct.size(), -1);   // first caller motif per distinct one
+        for (int32_t m = 0; m < tr->n_motifs; ++m)
+            if (first[tr->motif_q[m]] < 0) first[tr->motif_q[m]] = m;
+        uint64_t total = 0;
+        for (size_t q = 0; q < first.size(); ++q) total += cnt[first[q]];
+        if (!out || (uint64_t)capacity < total) {
+            *n_matches = (int64_t)total;
+            return MG_OK;
+        }
+        hipStream_t st = (hipStream_t)stream;
+        DevBuf d_work, d_rec;
+        struct G { DevBuf *a, *b; ~G() { dev_free(*a); dev_free(*b); } } guard{&d_work, &d_rec};
+        const size_t cnt_off = kQueueBytes, cur_off = cnt_off + 8 * n_slots(tr);
+        rc = dev_alloc(d_work, cur_off + 8, (void *)st);
+        if (!rc) rc = dev_alloc(d_rec, sizeof(mg_match) * std::max<uint64_t>(total, 1), (void *)st);
+        if (rc) return rc;
+        HIP_TRY(hipMemsetAsync(d_work.ptr, 0, cur_off + 8, st));
+        unsigned long long *w = (unsigned long long *)d_work.ptr;
+        o.leaf_scan = -1;   // every match goes through the candidate expansion
+        hipError_t e = hipSuccess;
+        if (g->E > 0) {
+            if (g->time_bytes == 4) {
+                mg::KParams<uint32_t> p{};
+                fill_params<uint32_t>(p, g, tr, o, w, w + cnt_off / 8, nullptr, nullptr);
+                p.enum_out = (int32_t *)d_rec.ptr;
+                p.enum_cursor = w + cur_off / 8;
+                p.enum_cap = total;
+                e = mg::launch_comine<uint32_t>(p, 0, st);
+            } else {
+                mg::KParams<uint64_t> p{};
+                fill_params<uint64_t>(p, g, tr, o, w, w + cnt_off / 8, nullptr, nullptr);
+                p.enum_out = (int32_t *)d_rec.ptr;
+                p.enum_cursor = w + cur_off / 8;
+                p.enum_cap = total;
+                e = mg::launch_comine<uint64_t>(p, 0, st);
+            }
+        }
+        if (e != hipSuccess) return fail(MG_EDEVICE, "enumeration launch failed: %s", hipGetErrorString(e));
+        uint64_t written = 0;
+        HIP_TRY(hipMemcpyAsync(&written, w + cur_off / 8, 8, hipMemcpyDeviceToHost, st));
+        if (total) HIP_TRY(hipMemcpyAsync(out, d_rec.ptr, sizeof(mg_match) * total, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (written != total)
+            return fail(MG_EINTERNAL, "enumeration wrote %llu matches, the count is %llu",
+                        (unsigned long long)written, (unsigned long long)total);
+        // motifs in the caller's numbering (a duplicate's first occurrence),
+        // edges in the caller's input order
+        for (uint64_t i = 0; i < total; ++i) {
+            mg_match &m = out[i];
+            m.motif = first[m.motif];
+            if (!g->input_index.empty())
+                for (int j = 0; j < mg::kKMax && m.edges[j] >= 0; ++j)
+                    m.edges[j] = (int32_t)g->input_index[m.edges[j]];
+        }
+        *n_matches = (int64_t)total;
+        return MG_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(MG_ENOMEM, "out of host memory");
+    } catch (...) {
+        return fail(MG_EINTERNAL, "unexpected exception");
+    }
+}
+
 int mg_count_noalloc(const mg_graph *g, const mg_tree *tr, const mg_count_opts *opts,
                      uint64_t *counts) {
     try {
         if (!g || !tr || !counts) return fail(MG_EINVAL, "NULL argument");
+        if (g->host_only) return fail(MG_EINVAL, "the graph is on the host only (MG_HOST_ONLY)");
         mg_count_opts o;
         mg_count_opts_init(&o);
         if (opts) o = *opts;
         if (o.mode != MG_MODE_COMINE || o.sched != MG_SCHED_PLAIN || o.roots || o.root_cost ||
-            o.elapsed_ms || o.cursor)
+            o.elapsed_ms || o.cursor || o.wave_clock)
             return fail(MG_EINVAL, "mg_count_noalloc takes co-mining with the plain schedule over "
                                    "every root; roots, root_cost, elapsed_ms and cursor need memory");
         if (o.chunk < 0 || (o.chunk % 64) != 0 || o.chunk > (1 << 16))
@@ -1442,10 +1503,17 @@ int mg_count(const mg_graph *g, const mg_tree *tr_c, const mg_count_opts *opts,
              uint64_t *counts) {
     try {
         if (!g || !tr_c || !counts) return fail(MG_EINVAL, "NULL argument");
+        if (g->host_only) return fail(MG_EINVAL, "the graph is on the host only (MG_HOST_ONLY)");
         mg_tree *tr = const_cast<mg_tree *>(tr_c);   // device copy is a cache
         mg_count_opts o;
         mg_count_opts_init(&o);
         if (opts) o = *opts;
+        if (o.mode == MG_MODE_AUTO) {
+            mg_advice a{};
+            int rc = mg_comine_advice(g, tr, MG_PLATFORM_GPU, &a);
+            if (rc) return rc;
+            o.mode = a.co_mine ? MG_MODE_COMINE : MG_MODE_PER_MOTIF;
+        }
         if (o.mode != MG_MODE_COMINE && o.mode != MG_MODE_PER_MOTIF)
             return fail(MG_EINVAL, "unknown mode %d", o.mode);
         if (o.chunk < 0 || (o.chunk % 64) != 0 || o.chunk > (1 << 16))
@@ -1455,6 +1523,8 @@ int mg_count(const mg_graph *g, const mg_tree *tr_c, const mg_count_opts *opts,
             return fail(MG_EINVAL, "queues must be in [0, %d]", mg::kQueues);
         if (o.stats && o.root_cost)
             return fail(MG_EINVAL, "stats and root_cost are exclusive");
+        if (o.wave_clock && (o.mode != MG_MODE_COMINE || o.wave_clock_len < 0))
+            return fail(MG_EINVAL, "wave_clock needs co-mining and a length >= 0");
         if (o.sched != MG_SCHED_PLAIN && o.sched != MG_SCHED_LEARNED)
             return fail(MG_EINVAL, "unknown schedule %d", o.sched);
         if (o.max_chunks < 0 || o.max_chunks > 0xffffffffll)
@@ -1511,14 +1581,8 @@ int mg_count(const mg_graph *g, const mg_tree *tr_c, const mg_count_opts *opts,
         if (o.mode == MG_MODE_COMINE) {
             runs.push_back(tr);
         } else {
-            if (tr->singles.empty()) {
-                for (const Motif &m : tr->distinct) {
-                    mg_tree *one = nullptr;
-                    int rc = make_tree({m}, tr->deltas, &one);
-                    if (rc) return rc;
-                    tr->singles.emplace_back(one);
-                }
-            }
+            int rc = chain_trees(tr);
+            if (rc) return rc;
             for (auto &u : tr->singles) runs.push_back(u.get());
         }
         size_t maxq = 1;
@@ -1541,6 +1605,13 @@ int mg_count(const mg_graph *g, const mg_tree *tr_c, const mg_count_opts *opts,
             if (g->E) HIP_TRY(hipMemsetAsync(d_cost.ptr, 0, sizeof(uint64_t) * (size_t)g->E, st));
         }
         struct Guard3 { DevBuf *b; ~Guard3() { dev_free(*b); } } gc{&d_cost};
+        DevBuf d_clock;
+        if (o.wave_clock && o.wave_clock_len >= 2) {
+            rc = dev_alloc(d_clock, 8 * (size_t)o.wave_clock_len, (void *)st);
+            if (rc) return rc;
+            HIP_TRY(hipMemsetAsync(d_clock.ptr, 0, 8 * (size_t)o.wave_clock_len, st));
+        }
+        struct Guard4 { DevBuf *b; ~Guard4() { dev_free(*b); } } gk{&d_clock};
 
         std::vector<uint64_t> qcount(n_slots(tr), 0);
         float total_ms = 0.f;
@@ -1553,11 +1624,13 @@ int mg_count(const mg_graph *g, const mg_tree *tr_c, const mg_count_opts *opts,
             rc = g->time_bytes == 4
                      ? launch_tree<uint32_t>(g, t, (const uint32_t *)d_roots.ptr, n_roots,
                                              d_queues, d_counts, d_stats,
-                                             (unsigned long long *)d_cost.ptr, o, st,
+                                             (unsigned long long *)d_cost.ptr,
+                                             (unsigned long long *)d_clock.ptr, o, st,
                                              o.elapsed_ms ? &ms : nullptr)
                      : launch_tree<uint64_t>(g, t, (const uint32_t *)d_roots.ptr, n_roots,
                                              d_queues, d_counts, d_stats,
-                                             (unsigned long long *)d_cost.ptr, o, st,
+                                             (unsigned long long *)d_cost.ptr,
+                                             (unsigned long long *)d_clock.ptr, o, st,
                                              o.elapsed_ms ? &ms : nullptr);
             if (rc) return rc;
             total_ms += ms;
@@ -1593,6 +1666,11 @@ int mg_count(const mg_graph *g, const mg_tree *tr_c, const mg_count_opts *opts,
         map_counts(tr, qcount.data(), counts);
         if (o.root_cost && g->E) {
             HIP_TRY(hipMemcpyAsync(o.root_cost, d_cost.ptr, sizeof(uint64_t) * (size_t)g->E,
+                                   hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+        }
+        if (d_clock.ptr) {
+            HIP_TRY(hipMemcpyAsync(o.wave_clock, d_clock.ptr, 8 * (size_t)o.wave_clock_len,
                                    hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
         }
@@ -1677,6 +1755,7 @@ int mg_tune(const mg_graph *g, const mg_tree *tr, const char *cache_path, void *
             mg_tune_result *out) {
     try {
         if (!g || !tr || !out) return fail(MG_EINVAL, "NULL argument");
+        if (g->host_only) return fail(MG_EINVAL, "the graph is on the host only (MG_HOST_ONLY)");
         const std::string key = tune_key(g, tr);
         mg_tune_result best{};
         if (cache_path && cache_lookup(cache_path, key, &best)) {

@@ -210,11 +210,71 @@ __device__ __forceinline__ uint32_t leaf_scan_wave(const KParams<TT> &p, const i
     return got + credit_child(gb.w, len - hit, cnt, nd, j, move);
 }
 
+// The same for a tree with several windows: the whole window counts at the
+// largest window, and each smaller window, a prefix of it whose length the
+// same pass measures (entries with t <= t_first + its delta, one ballot per
+// window), moves its matches down one slot with a second, shorter pass.
+// tf: the partial match's first time.
+template <typename TT, int SA>
+__device__ __forceinline__ uint32_t leaf_scan_wave_multi(const KParams<TT> &p,
+                                                         const int32_t (&ph)[SA], uint32_t g,
+                                                         uint32_t l0, uint32_t len, TT tf,
+                                                         const int lane, unsigned long long *cnt,
+                                                         uint32_t nd) {
+    const uint4 ga = p.tree.grp[2 * g], gb = p.tree.grp[2 * g + 1];
+    const uint32_t nvp = (ga.x >> 8) & 15;
+    const Entry<TT> *__restrict__ e =
+        ((ga.x & 15) == kDirOut ? p.g.out_adj : p.g.in_adj) + l0;
+    int32_t q[SA];
+    uint32_t c[SA];
+#pragma unroll
+    for (int s = 0; s < SA; ++s) {
+        q[s] = (uint32_t)s < nvp ? ph[s] : -1;
+        c[s] = 0;
+    }
+    TT thr[kMaxDeltas - 1];
+    uint32_t pre[kMaxDeltas - 1];
+#pragma unroll
+    for (int j = 0; j < kMaxDeltas - 1; ++j) {
+        thr[j] = sat_add(tf, p.dlo[j]);
+        pre[j] = 0;
+    }
+    for (uint32_t i = 0; i < len; i += kWave) {
+        const bool in = i + lane < len;
+        Entry<TT> en{};
+        if (in) en = e[i + lane];
+        const int32_t v = in ? en.v : -2;   // -2 matches no slot
+#pragma unroll
+        for (int s = 0; s < SA; ++s) c[s] += (uint32_t)__popcll(__ballot(v == q[s]));
+#pragma unroll
+        for (int j = 0; j < kMaxDeltas - 1; ++j)
+            if ((uint32_t)j + 1 < nd) pre[j] += (uint32_t)__popcll(__ballot(in && en.t <= thr[j]));
+    }
+    uint32_t got = 0;
+    if (lane == 0) {
+        const uint32_t words[6] = {ga.y, ga.z, ga.w, gb.x, gb.y, gb.z};
+        uint32_t hit = 0;
+#pragma unroll
+        for (int s = 0; s < SA; ++s) {
+            hit += c[s];
+            got += credit_child(words[s], c[s], cnt, nd, nd - 1);
+        }
+        got += credit_child(gb.w, len - hit, cnt, nd, nd - 1);
+    }
+#pragma unroll
+    for (int j = kMaxDeltas - 2; j >= 0; --j)
+        if ((uint32_t)j + 1 < nd && pre[j] > 0)
+            leaf_scan_wave<TT, SA>(p, ph, g, l0, pre[j], lane, cnt, nd, (uint32_t)j, true);
+    return got;
+}
+
 // Partial matches with L motif edges matched.  Level 1 is the root batch:
 // every entry is at the trie root and its last edge is its first, so it keeps
 // only the two bound vertices and the root time.
-// (R: the per-root cost log keeps each partial match's root edge.)
-template <typename TT, int L, bool R>
+// R: 1 = each partial match also keeps its root edge (the per-root cost log),
+// 2 = its root edge and the slot of its parent one level up (enumeration,
+// which writes out every matched edge).
+template <typename TT, int L, int R>
 struct LevelBuf {
     static constexpr int S = (2 * L < kVMax) ? 2 * L : kVMax;   // vertex slots
     static constexpr int C = 2 * kWave;                          // capacity
@@ -227,8 +287,9 @@ struct LevelBuf {
     uint16_t pincl1[C];    // lists of motif vertex 0 or 1, then the others
     uint8_t r1[C];         // slot of its root in the level-1 batch
     uint32_t root[R ? C : 1];
+    uint8_t par[R == 2 && L > 2 ? C : 1];   // slot of its parent at level L - 1
 };
-template <typename TT, bool R>
+template <typename TT, int R>
 struct LevelBuf<TT, 1, R> {
     static constexpr int S = 2;
     static constexpr int C = kWave;
@@ -237,12 +298,12 @@ struct LevelBuf<TT, 1, R> {
     uint32_t root[R ? kWave : 1];
 };
 
-template <typename TT, int D, bool R, int L>
+template <typename TT, int D, int R, int L>
 struct LevelChain {
     LevelBuf<TT, L, R> buf;
     LevelChain<TT, D, R, L + 1> next;
 };
-template <typename TT, int D, bool R>
+template <typename TT, int D, int R>
 struct LevelChain<TT, D, R, D> {};
 
 // per-wave LDS: level buffers plus small scratch tables.  Its size is a
@@ -256,7 +317,7 @@ struct LevelChain<TT, D, R, D> {};
 // list with t_prev < t <= t_first + delta, t_prev > t_first: it starts inside
 // the root's window and ends where it ends, so a bisection over the root's
 // window replaces a bisection over the whole list and the search for the end.
-template <typename TT, int D, bool R>
+template <typename TT, int D, int R>
 struct alignas(16) WaveLds {
     static constexpr int H = D > 1 ? 4 : 1;
     uint8_t src[kWave];           // window compaction: lane holding the k-th window
@@ -266,17 +327,17 @@ struct alignas(16) WaveLds {
     LevelChain<TT, D, R, 1> lv;
 };
 
-static_assert(sizeof(WaveLds<uint32_t, 1, false>) % 16 == 0, "per-wave LDS block size");
-static_assert(sizeof(WaveLds<uint32_t, 3, false>) % 16 == 0, "per-wave LDS block size");
-static_assert(sizeof(WaveLds<uint32_t, 5, false>) % 16 == 0, "per-wave LDS block size");
-static_assert(sizeof(WaveLds<uint64_t, 5, true>) % 16 == 0, "per-wave LDS block size");
+static_assert(sizeof(WaveLds<uint32_t, 1, 0>) % 16 == 0, "per-wave LDS block size");
+static_assert(sizeof(WaveLds<uint32_t, 3, 0>) % 16 == 0, "per-wave LDS block size");
+static_assert(sizeof(WaveLds<uint32_t, 5, 0>) % 16 == 0, "per-wave LDS block size");
+static_assert(sizeof(WaveLds<uint64_t, 5, 1>) % 16 == 0, "per-wave LDS block size");
 
 constexpr uint16_t kNoHint = 0xffff;
 
 // A new root a -> b in level-1 slot `slot`: its root windows are not found
 // yet; their first-entry words hold where they start, the first entries
 // after the root's time in out(a), in(a), out(b) and in(b).
-template <typename TT, int D, bool R>
+template <typename TT, int D, int R>
 __device__ __forceinline__ void set_root_slot(WaveLds<TT, D, R> &W, uint32_t slot, uint4 gx) {
     W.hlo[0][slot] = gx.x;
     W.hlo[1][slot] = gx.y;
@@ -286,10 +347,50 @@ __device__ __forceinline__ void set_root_slot(WaveLds<TT, D, R> &W, uint32_t slo
     for (int k = 0; k < 4; ++k) W.hlen[k][slot] = kNoHint;
 }
 
-template <int L, typename TT, int D, bool R, int M>
+template <int L, typename TT, int D, int R, int M>
 __device__ __forceinline__ LevelBuf<TT, L, R> &lvl(LevelChain<TT, D, R, M> &c) {
     if constexpr (L == M) return c.buf;
     else return lvl<L>(c.next);
+}
+
+// What the level buffers keep per partial match beyond the search itself
+// (the R of LevelBuf) in each kernel MODE.
+constexpr int keep_of(int mode) { return mode == 2 ? 1 : mode == 4 ? 2 : 0; }
+
+// Enumeration: the edge ids of partial match i at level L, first edge first,
+// into e[0..L), following the parent slots up to the root batch.
+template <int L, typename TT, int D>
+__device__ __forceinline__ void edge_chain(WaveLds<TT, D, 2> &W, uint32_t i, uint32_t (&e)[kKMax]) {
+    if constexpr (L == 1) {
+        e[0] = lvl<1>(W.lv).root[i];
+    } else {
+        LevelBuf<TT, L, 2> &A = lvl<L>(W.lv);
+        e[L - 1] = A.eid[i];
+        if constexpr (L == 2) edge_chain<1>(W, A.r1[i], e);
+        else edge_chain<L - 1>(W, A.par[i], e);
+    }
+}
+
+// Enumeration: writes one record per lane with `want` (motif q, then the
+// edges e[0..k) and -1 up to kKMax) at consecutive slots of the output, the
+// wave taking its slots with one atomic.  Slots past the capacity are
+// dropped (the caller sized the output from the count).
+template <typename TT>
+__device__ __forceinline__ void write_matches(const KParams<TT> &p, bool want, uint32_t q,
+                                              const uint32_t (&e)[kKMax], uint32_t k) {
+    const uint64_t m = __ballot(want);
+    if (!m) return;
+    unsigned long long base = 0;
+    if ((threadIdx.x & (kWave - 1)) == 0)
+        base = atomicAdd(p.enum_cursor, (unsigned long long)__popcll(m));
+    base = lane0_u64(base);
+    if (!want) return;
+    const unsigned long long slot = base + mbcnt(m);
+    if (slot >= p.enum_cap) return;
+    int32_t *rec = p.enum_out + slot * (1 + kKMax);
+    rec[0] = (int32_t)q;
+#pragma unroll
+    for (int i = 0; i < kKMax; ++i) rec[1 + i] = (uint32_t)i < k ? (int32_t)e[i] : -1;
 }
 
 // per-lane statistics (only the STATS instantiation touches them)
@@ -298,21 +399,22 @@ struct Stats {
 };
 
 // MODE: 0 plain search (trees with one window), 1 with search statistics, 2
-// with the per-root cost log, 3 plain search of a tree with several windows
+// with the per-root cost log, 3 plain search of a tree with several windows,
+// 4 enumeration (every match written out)
 // At level 1 with nparts > 1 (one buffered root), only part `part` of the
 // root's candidates is expanded: [T * part / nparts, T * (part + 1) / nparts)
 // of its T candidates in window order, so that the parts of one root
 // partition its search exactly; windows that a single lane counts, and the
 // root's window statistics, belong to part 0.
 template <typename TT, int D, int MODE, int L>
-__device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, MODE == 2> &W,
+__device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, keep_of(MODE)> &W,
                                           unsigned long long *cnt, const int lane,
                                           const uint32_t nA, Stats &st, const uint32_t part = 0,
                                           const uint32_t nparts = 1) {
     constexpr bool STATS = MODE == 1, LOG = MODE == 2;
-    LevelBuf<TT, L, LOG> &A = lvl<L>(W.lv);
-    constexpr int SA = LevelBuf<TT, L, LOG>::S;
-    LevelBuf<TT, 1, LOG> &R1 = lvl<1>(W.lv);
+    LevelBuf<TT, L, keep_of(MODE)> &A = lvl<L>(W.lv);
+    constexpr int SA = LevelBuf<TT, L, keep_of(MODE)>::S;
+    LevelBuf<TT, 1, keep_of(MODE)> &R1 = lvl<1>(W.lv);
     // graph vertex of motif vertex s, and t_first, of buffered partial match i
     auto vtx = [&](uint32_t s, uint32_t i) -> int32_t {
         if constexpr (L == 1) return A.phi[s][i];
@@ -551,19 +653,12 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                     const uint32_t wg = __builtin_amdgcn_readlane(g, src);
                     const uint32_t wl0 = __builtin_amdgcn_readlane(l0, src);
                     const uint32_t wlen = __builtin_amdgcn_readlane(len, src);
-                    const uint32_t c = leaf_scan_wave<TT, SA>(p, wph, wg, wl0, wlen, lane, cnt, nd,
-                                                              nd - 1);
-                    if constexpr (MODE != 0) {
-                        const TT *ta = times_of((grp[2 * wg].x & 15) == kDirOut ? p.g.out_adj
-                                                                                : p.g.in_adj);
-                        const TT tf = tfirst_of(wx);
-                        uint32_t e = wl0 + wlen;
-                        for (uint32_t j = nd - 1; j-- > 0;) {
-                            e = uniform(gallop_greater(ta, 1, wl0, e, sat_add(tf, window_lo(p, j))));
-                            if (e == wl0) break;
-                            leaf_scan_wave<TT, SA>(p, wph, wg, wl0, e - wl0, lane, cnt, nd, j, true);
-                        }
-                    }
+                    uint32_t c;
+                    if (nd == 1)
+                        c = leaf_scan_wave<TT, SA>(p, wph, wg, wl0, wlen, lane, cnt, 1u, 0u);
+                    else
+                        c = leaf_scan_wave_multi<TT, SA>(p, wph, wg, wl0, wlen, tfirst_of(wx), lane,
+                                                         cnt, nd);
                     if constexpr (STATS) st.v[kStatCredit] += c;
                 }
                 // compact the other non-empty windows into lanes 0..nw-1; their
@@ -665,9 +760,21 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                 }
                 if constexpr (STATS) st.v[kStatCredit] += 1;
             }
+            // the edge id of this candidate (pushed along, and written out
+            // when enumerating), read only where it is used
+            auto cand_eid = [&]() -> uint32_t {
+                return dir == kDirAll ? ei : (dir == kDirOut ? p.g.out_eid : p.g.in_eid)[ei];
+            };
+            if constexpr (MODE == 4) {
+                const uint32_t q1 = (cw >> 16) & 0x7fffu;
+                uint32_t e[kKMax] = {0, 0, 0, 0, 0};
+                edge_chain<L>(W, ox, e);
+                e[L] = valid ? cand_eid() : 0u;
+                write_matches(p, valid && cw && q1, q1 - 1u, e, L + 1);
+            }
             if constexpr (L + 1 < D) {
-                LevelBuf<TT, L + 1, LOG> &B = lvl<L + 1>(W.lv);
-                constexpr int SB = LevelBuf<TT, L + 1, LOG>::S;
+                LevelBuf<TT, L + 1, keep_of(MODE)> &B = lvl<L + 1>(W.lv);
+                constexpr int SB = LevelBuf<TT, L + 1, keep_of(MODE)>::S;
                 const bool push = (cw >> 31) != 0;
                 const uint64_t pm = __ballot(push);
                 if (push) {
@@ -679,12 +786,12 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
                             : ((uint32_t)s == nvp ? nv0 : ((uint32_t)s == nvp + 1 ? nv1 : -1));
                         B.phi[s - 2][slot] = v;
                     }
-                    B.eid[slot] = dir == kDirAll ? ei
-                                                 : (dir == kDirOut ? p.g.out_eid : p.g.in_eid)[ei];
+                    B.eid[slot] = cand_eid();
                     B.node[slot] = (uint16_t)(cw & 0xffffu);
                     if constexpr (L == 1) B.r1[slot] = (uint8_t)ox;
                     else B.r1[slot] = A.r1[ox];
-                    if constexpr (LOG) B.root[slot] = A.root[ox];
+                    if constexpr (keep_of(MODE) > 0) B.root[slot] = A.root[ox];
+                    if constexpr (keep_of(MODE) == 2 && L > 1) B.par[slot] = (uint8_t)ox;
                     if constexpr (STATS) st.v[kStatPush] += 1;
                 }
                 nB += (uint32_t)__popcll(pm);
@@ -707,7 +814,7 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, M
 // split items come only with p.roots NULL); part 0 credits the root itself.
 template <typename TT, int D, int MODE>
 __device__ __forceinline__ void process_root_part(const KParams<TT> &p,
-                                                  WaveLds<TT, D, MODE == 2> &W,
+                                                  WaveLds<TT, D, keep_of(MODE)> &W,
                                                   unsigned long long *cnt, const int lane,
                                                   const uint32_t r, const uint32_t part,
                                                   const uint32_t nparts, Stats &st) {
@@ -722,13 +829,13 @@ __device__ __forceinline__ void process_root_part(const KParams<TT> &p,
         }
     }
     if constexpr (D > 1) {
-        LevelBuf<TT, 1, LOG> &A = lvl<1>(W.lv);
+        LevelBuf<TT, 1, keep_of(MODE)> &A = lvl<1>(W.lv);
         if (lane == 0) {
             A.phi[0][0] = s;
             A.phi[1][0] = d;
             A.tfirst[0] = p.g.gt[r];
             set_root_slot(W, 0, p.g.gx[r]);
-            if constexpr (LOG) A.root[0] = r;
+            if constexpr (keep_of(MODE) > 0) A.root[0] = r;
         }
         wave_sync();
         run_level<TT, D, MODE, 1>(p, W, cnt, lane, 1u, st, part, nparts);
@@ -740,7 +847,7 @@ __device__ __forceinline__ void process_root_part(const KParams<TT> &p,
 // p.roots is NULL), 64 at a time.
 template <typename TT, int D, int MODE>
 __device__ __forceinline__ void process_roots(const KParams<TT> &p,
-                                              WaveLds<TT, D, MODE == 2> &W,
+                                              WaveLds<TT, D, keep_of(MODE)> &W,
                                               unsigned long long *cnt, const int lane,
                                               const uint32_t base, const uint32_t end,
                                               Stats &st) {
@@ -759,19 +866,25 @@ __device__ __forceinline__ void process_roots(const KParams<TT> &p,
         const uint64_t m = __ballot(ok);
         if (p.tree.root_q >= 0 && lane == 0 && m)
             atomicAdd(&cnt[p.tree.root_q * p.tree.n_d], (unsigned long long)__popcll(m));
+        if constexpr (MODE == 4) {
+            if (p.tree.root_q >= 0) {
+                uint32_t e[kKMax] = {r, 0, 0, 0, 0};
+                write_matches(p, ok, (uint32_t)p.tree.root_q, e, 1);
+            }
+        }
         if constexpr (STATS) st.v[kStatRoots] += ok ? 1 : 0;
         if constexpr (LOG) {
             if (ok) atomicAdd(&p.root_cost[r], 1ull);
         }
         if constexpr (D > 1) {
-            LevelBuf<TT, 1, LOG> &A = lvl<1>(W.lv);
+            LevelBuf<TT, 1, keep_of(MODE)> &A = lvl<1>(W.lv);
             if (ok) {
                 const uint32_t slot = mbcnt(m);
                 A.phi[0][slot] = s;
                 A.phi[1][slot] = d;
                 A.tfirst[slot] = p.g.gt[r];
                 set_root_slot(W, slot, p.g.gx[r]);
-                if constexpr (LOG) A.root[slot] = r;
+                if constexpr (keep_of(MODE) > 0) A.root[slot] = r;
             }
             const uint32_t n1 = uniform((uint32_t)__popcll(m));
             if (n1 > 0) {
@@ -802,7 +915,7 @@ comine_kernel(const KParams<TT> p) {
     const size_t cnt_bytes = ((size_t)n_slots * 8 + 15) & ~(size_t)15;
     const int lane = (int)(threadIdx.x & (kWave - 1));
     const int wave = (int)(threadIdx.x / kWave);
-    WaveLds<TT, D, LOG> &W = reinterpret_cast<WaveLds<TT, D, LOG> *>(smem + cnt_bytes)[wave];
+    WaveLds<TT, D, keep_of(MODE)> &W = reinterpret_cast<WaveLds<TT, D, keep_of(MODE)> *>(smem + cnt_bytes)[wave];
 
     for (int i = (int)threadIdx.x; i < n_slots; i += (int)blockDim.x) cnt[i] = 0;
     W.flag[lane] = 0;
@@ -810,6 +923,10 @@ comine_kernel(const KParams<TT> p) {
     Stats st;
 #pragma unroll
     for (int i = 0; i < kStats; ++i) st.v[i] = 0;
+    // when each wave starts and ends its search (device real-time clock)
+    const uint32_t clock_slot = blockIdx.x * kWavesPerBlock + (uint32_t)wave;
+    if (p.wave_clock && lane == 0 && clock_slot < p.n_wave_clock)
+        p.wave_clock[2 * clock_slot] = __builtin_amdgcn_s_memrealtime();
 
     if (p.items) {
         // scheduled work items first, claimed in order from their own queue
@@ -870,6 +987,8 @@ comine_kernel(const KParams<TT> p) {
         }
     }
 
+    if (p.wave_clock && lane == 0 && clock_slot < p.n_wave_clock)
+        p.wave_clock[2 * clock_slot + 1] = __builtin_amdgcn_s_memrealtime();
     if constexpr (STATS) {
 #pragma unroll
         for (int i = 0; i < kStats; ++i)
@@ -890,9 +1009,9 @@ batch_kernel(const BatchParams<TT> bp) {
     const int lane = (int)(threadIdx.x & (kWave - 1));
     const int wave = (int)(threadIdx.x / kWave);
     const size_t cnt_bytes = ((size_t)bp.n_q_max * 8 + 15) & ~(size_t)15;
-    unsigned char *mine = smem + (size_t)wave * (cnt_bytes + sizeof(WaveLds<TT, D, false>));
+    unsigned char *mine = smem + (size_t)wave * (cnt_bytes + sizeof(WaveLds<TT, D, 0>));
     unsigned long long *cnt = reinterpret_cast<unsigned long long *>(mine);
-    WaveLds<TT, D, false> &W = *reinterpret_cast<WaveLds<TT, D, false> *>(mine + cnt_bytes);
+    WaveLds<TT, D, 0> &W = *reinterpret_cast<WaveLds<TT, D, 0> *>(mine + cnt_bytes);
     W.flag[lane] = 0;
     Stats st;
     for (;;) {
@@ -934,7 +1053,7 @@ batch_kernel(const BatchParams<TT> bp) {
 template <typename TT, int D, int MODE>
 size_t smem_bytes(int n_q) {
     return (((size_t)n_q * 8 + 15) & ~(size_t)15) +
-           (size_t)kWavesPerBlock * sizeof(WaveLds<TT, D, MODE == 2>);
+           (size_t)kWavesPerBlock * sizeof(WaveLds<TT, D, keep_of(MODE)>);
 }
 
 template <typename TT, int D, int MODE>
@@ -964,6 +1083,7 @@ hipError_t launch_ds(const KParams<TT> &p, int blocks, hipStream_t stream) {
 
 template <typename TT, int D>
 hipError_t launch_d(const KParams<TT> &p, int blocks, hipStream_t stream) {
+    if (p.enum_out) return launch_ds<TT, D, 4>(p, blocks, stream);
     if (p.stats) return launch_ds<TT, D, 1>(p, blocks, stream);
     if (p.root_cost) return launch_ds<TT, D, 2>(p, blocks, stream);
     if (p.tree.n_d > 1) return launch_ds<TT, D, 3>(p, blocks, stream);
@@ -973,7 +1093,7 @@ hipError_t launch_d(const KParams<TT> &p, int blocks, hipStream_t stream) {
 template <typename TT, int D, int MODE>
 hipError_t launch_batch_d(const BatchParams<TT> &bp, int blocks, hipStream_t stream) {
     const size_t sm = (size_t)kWavesPerBlock *
-                      ((((size_t)bp.n_q_max * 8 + 15) & ~(size_t)15) + sizeof(WaveLds<TT, D, false>));
+                      ((((size_t)bp.n_q_max * 8 + 15) & ~(size_t)15) + sizeof(WaveLds<TT, D, 0>));
     auto kern = batch_kernel<TT, D, MODE>;
     if (sm > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)kern,

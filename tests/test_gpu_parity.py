@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from paper_2507_14813_amd import api, workloads as W
-from oracle import OracleGraph
+from oracle import OracleGraph, brute
 from conftest import edges_of, tiny_graph
 
 pytestmark = pytest.mark.gpu
@@ -152,6 +152,67 @@ def test_multi_window_medium_every_path():
         assert np.array_equal(a, want) and np.array_equal(c, oracle_counts(og, ms[:7], 11))
     say("multi-window noalloc")
     assert np.array_equal(api.count_noalloc(g, tr), want)
+
+
+def _records(motif, edges):
+    return sorted((int(m),) + tuple(int(x) for x in e if x >= 0) for m, e in zip(motif, edges))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_enumeration_equals_brute_force(seed):
+    """Every match written out by the search equals the brute-force list of
+    the definition on tiny graphs (ties, self-loops, unsorted input), for
+    every motif with k <= 3 and sampled four- and five-edge motifs; the
+    hand-listed matches of Example A come out as listed."""
+    rng = np.random.default_rng(600 + seed)
+    n = int(rng.integers(3, 7))
+    s, d, t = tiny_graph(rng, n, int(rng.integers(8, 13)), 8, self_loops=seed != 1)
+    perm = rng.permutation(len(s))
+    s, d, t = s[perm], d[perm], t[perm]
+    ms = _tiny_motifs()[::3] + [[(0, 1), (2, 3)], [(0, 1), (0, 1)]]
+    g = api.Graph(s, d, t, n)
+    for delta in (0, 4, BIG):
+        say("enumerate tiny", seed, delta)
+        tr = api.Tree(ms + [ms[0]], delta)           # a duplicate motif
+        motif, edges = api.enumerate_matches(g, tr)
+        want = sorted((i,) + tup for i, m in enumerate(ms) for tup in brute.matches(s, d, t, m, delta))
+        assert _records(motif, edges) == want
+
+
+def test_enumeration_golden_and_medium(golden_examples):
+    A = golden_examples[0]
+    s, d, t, n = edges_of(A)
+    cases = [c for c in A["cases"] if "matches" in c]
+    g = api.Graph(s, d, t, n)
+    tr = api.Tree([[tuple(e) for e in c["motif"]] for c in cases], 30)
+    motif, edges = api.enumerate_matches(g, tr)
+    assert _records(motif, edges) == sorted((i,) + tuple(x) for i, c in enumerate(cases)
+                                            for x in c["matches"])
+    # medium graph: as many records per motif as the oracle counts, every one
+    # a match, no record twice
+    s, d, t, n, ms = _medium(seed=5, E=3000, V=25, tmax=500)
+    og = OracleGraph(s, d, t, n)
+    want = oracle_counts(og, ms, 20)
+    g = api.Graph(s, d, t, n)
+    say("enumerate medium")
+    motif, edges = api.enumerate_matches(g, api.Tree(ms, 20))
+    # a duplicate motif's matches are reported under its first occurrence
+    first = {}
+    exp = np.zeros(len(ms), np.uint64)
+    for i, m in enumerate(ms):
+        if tuple(map(tuple, m)) not in first:
+            first[tuple(map(tuple, m))] = i
+            exp[i] = want[i]
+    assert len(first) < len(ms)
+    assert np.array_equal(np.bincount(motif, minlength=len(ms)).astype(np.uint64), exp)
+    recs = _records(motif, edges)
+    assert len(set(recs)) == len(recs)
+    rng = np.random.default_rng(1)
+    for i in rng.choice(len(recs), min(len(recs), 3000), replace=False):
+        m, *es = recs[i]
+        assert brute.is_match([(int(s[x]), int(d[x]), int(t[x])) for x in es], ms[m], 20)
+    with pytest.raises(api.MayuraError, match="MG_EUNSUPPORTED"):
+        api.enumerate_matches(g, api.Tree(ms, [5, 20]))
 
 
 def test_autotuner_and_its_cache(tmp_path):

@@ -22,6 +22,31 @@ def test_golden_examples(oracle_mod, golden_examples):
             assert brute.count(s, d, t, m, c["delta"]) == c["count"], (ex["name"], c)
 
 
+def test_enumeration_oracle_pins(oracle_mod, golden_examples):
+    """The brute-force enumeration lists exactly the hand-listed tuples of
+    Example A, and on random tiny graphs (unsorted input, ties, self-loops)
+    as many tuples as the C oracle counts, each one a match of the motif."""
+    A = golden_examples[0]
+    s, d, t, n = edges_of(A)
+    for c in A["cases"]:
+        if "matches" in c:
+            m = [tuple(e) for e in c["motif"]]
+            assert brute.matches(s, d, t, m, c["delta"]) == [tuple(x) for x in c["matches"]]
+    rng = np.random.default_rng(77)
+    for _ in range(4):
+        nv = int(rng.integers(3, 6))
+        s, d, t = tiny_graph(rng, nv, int(rng.integers(8, 13)), 9, self_loops=True)
+        perm = rng.permutation(len(s))
+        s, d, t = s[perm], d[perm], t[perm]
+        for m in _tiny_motifs()[::7]:
+            for delta in (0, 3, BIG):
+                got = brute.matches(s, d, t, m, delta)
+                assert len(got) == oracle_mod.count(s, d, t, nv, m, delta)
+                for tup in got:
+                    assert brute.is_match([(int(s[i]), int(d[i]), int(t[i])) for i in tup], m, delta)
+                    assert all(t[a] < t[b] for a, b in zip(tup, tup[1:]))
+
+
 def _tiny_motifs():
     ms = []
     for k in (1, 2, 3):
