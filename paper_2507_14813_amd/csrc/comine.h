@@ -33,12 +33,20 @@ __host__ __device__ inline uint32_t queue_end(uint32_t n_roots, uint32_t n_queue
 }
 constexpr uint32_t kLeafScanDefault = 256;   // lane-counted leaf window limit
 
+// fields of an internal-node word (see below)
+__host__ __device__ inline uint32_t node_groups(uint32_t w) { return (w >> 20) & 31u; }
+__host__ __device__ inline uint32_t node_near(uint32_t w) { return (w >> 25) & 31u; }
+constexpr uint32_t kLeafParent = 1u << 30;
+static_assert(2 * kVMax + 1 < 32, "groups of a node fit 5 bits");
+
 // group direction: which adjacency list holds the candidates
 enum : int { kDirOut = 0, kDirIn = 1, kDirAll = 2 };
 
 // Search tables, as uploaded to the device.
 //   inode[i]  internal (non-leaf) trie node i: first group | group count << 20
-//             | count of the leading groups on a list of motif vertex 0 or 1 << 26
+//             | count of the leading groups on a list of motif vertex 0 or 1 << 25
+//             | leaf_parent << 30 (every child a leaf reached through a list
+//             of a bound vertex: all groups leaf_only)
 //   grp[2g], grp[2g+1]: eight words of group g:
 //     w0 = dir | anchor << 4 | nv << 8 | leaf_only << 12 | last_end << 13
 //          (nv: vertices bound at the owning node; leaf_only: a per-vertex

@@ -41,6 +41,14 @@ static __device__ __forceinline__ uint32_t incl_scan32(uint32_t x, int /*lane*/)
 static __device__ __forceinline__ uint32_t lane_value(uint32_t v, uint32_t src) {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)src);
 }
+static __device__ __forceinline__ uint32_t lane_time(uint32_t v, int src) {
+    return lane_value(v, (uint32_t)src);
+}
+static __device__ __forceinline__ uint64_t lane_time(uint64_t v, int src) {
+    const uint32_t lo = lane_value((uint32_t)v, (uint32_t)src);
+    const uint32_t hi = lane_value((uint32_t)(v >> 32), (uint32_t)src);
+    return ((uint64_t)hi << 32) | lo;
+}
 static __device__ __forceinline__ unsigned long long lane0_u64(unsigned long long v) {
     const uint32_t lo = lane_value((uint32_t)v, 0), hi = lane_value((uint32_t)(v >> 32), 0);
     return ((unsigned long long)hi << 32) | lo;

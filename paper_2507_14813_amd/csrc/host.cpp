@@ -319,8 +319,16 @@ int build_tree(mg_tree *tr) {
             }
             tr->grp_tab.insert(tr->grp_tab.end(), rec, rec + 8);
         }
+        // a leaf parent: every match below it is one more edge on a list of
+        // a bound vertex
+        bool leaf_parent = true;
+        for (int c : nd.kids) {
+            const TrieNode &ch = tr->nodes[c];
+            leaf_parent = leaf_parent && ch.kids.empty() && (ch.u < nd.nv || ch.v < nd.nv);
+        }
         tr->node_tab[iidx[n]] = (int32_t)((uint32_t)g0 | ((uint32_t)groups.size() << 20) |
-                                          ((uint32_t)n_near << 26));
+                                          ((uint32_t)n_near << 25) |
+                                          (leaf_parent ? mg::kLeafParent : 0u));
     }
     if (tr->grp_tab.empty()) tr->grp_tab.assign(8, 0);
     tr->root_q = tr->nodes[0].q;

@@ -31,6 +31,11 @@
 //     equality count per bound vertex (the list's own anchor left out), the
 //     new-vertex child taking the rest; a short one by its own lane, a long
 //     one by the whole wave with ballots.
+//   * A batch whose partial matches all sit at leaf parents (trie nodes
+//     whose children all end a motif, reached through lists of bound
+//     vertices) is taken one partial match per lane instead: the lane finds
+//     and counts the window of each of the node's groups in turn, with no
+//     pairing of partial matches and groups across the wave.
 //   * The other non-empty windows, up to 64 at a time, are expanded as one
 //     flat candidate range: lane i takes candidate c + i, finds its window
 //     from a 64-bit mask of window ends (LDS flags + ballot + popcount), reads
@@ -393,6 +398,153 @@ __device__ __forceinline__ void write_matches(const KParams<TT> &p, bool want, u
     for (int i = 0; i < kKMax; ++i) rec[1 + i] = (uint32_t)i < k ? (int32_t)e[i] : -1;
 }
 
+// Counts the leaf-only window [l0, l0 + len) of group g (header word hdr) for
+// one partial match by its own lane: ph[] are its bound vertices, tf its
+// first time.  nqm is the largest number of bound vertices compared by the
+// lanes counting together (the count loop is compiled for it).  Credits go to
+// the largest window, and with several windows each smaller one, a prefix of
+// this one, moves its matches down one slot.  Returns the credits.
+template <typename TT, int D, int MODE, int S>
+__device__ __forceinline__ uint32_t count_leaf_window(const KParams<TT> &p, uint32_t g,
+                                                      uint32_t hdr, const int32_t (&ph)[S],
+                                                      TT tf, uint32_t l0, uint32_t len,
+                                                      uint32_t nqm, unsigned long long *cnt,
+                                                      uint32_t nd) {
+    constexpr int NQ = S - 1;
+    const uint32_t anc = (hdr >> 4) & 15;
+    const uint32_t nq = ((hdr >> 8) & 15) - 1u;   // bound vertices, the anchor left out
+    const uint4 ga = p.tree.grp[2 * g], gb = p.tree.grp[2 * g + 1];
+    const uint32_t words[6] = {ga.y, ga.z, ga.w, gb.x, gb.y, gb.z};
+    int32_t q[NQ];
+    uint32_t w[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        // slot i below the anchor, slot i + 1 from it on
+        const bool below = (uint32_t)i < anc, on = (uint32_t)i < nq;
+        q[i] = on ? (below ? ph[i] : ph[i + 1]) : -1;
+        w[i] = on ? (below ? words[i] : words[i + 1]) : 0u;
+    }
+    const Entry<TT> *adj = (hdr & 15) == kDirOut ? p.g.out_adj : p.g.in_adj;
+    // loads per step (measured: 8 for trees up to depth 3, 4 deeper)
+    constexpr int kLU = D <= 3 ? 8 : 4;
+    auto count = [&](uint32_t n, uint32_t j, bool move) -> uint32_t {
+        uint32_t c = 0;
+        if constexpr (NQ >= 1) if (nqm == 1) c = leaf_count<kLU, 1>(adj, l0, n, q, w, gb.w, cnt, nd, j, move);
+        if constexpr (NQ >= 2) if (nqm == 2) c = leaf_count<kLU, 2>(adj, l0, n, q, w, gb.w, cnt, nd, j, move);
+        if constexpr (NQ >= 3) if (nqm == 3) c = leaf_count<kLU, 3>(adj, l0, n, q, w, gb.w, cnt, nd, j, move);
+        if constexpr (NQ >= 4) if (nqm == 4) c = leaf_count<kLU, 4>(adj, l0, n, q, w, gb.w, cnt, nd, j, move);
+        if constexpr (NQ >= 5) if (nqm == 5) c = leaf_count<kLU, 5>(adj, l0, n, q, w, gb.w, cnt, nd, j, move);
+        return c;
+    };
+    // the whole window counts at the largest window
+    const uint32_t c = count(len, nd - 1, false);
+    if constexpr (MODE != 0) {
+        // each smaller window is a prefix of this one: its matches move down
+        // one slot (usually it is empty)
+        const TT *ta = times_of(adj);
+        uint32_t e = l0 + len;
+        for (uint32_t j = nd - 1; j-- > 0;) {
+            e = gallop_greater(ta, 1, l0, e, sat_add(tf, window_lo(p, j)));
+            if (e == l0) break;
+            count(e - l0, j, true);
+        }
+    }
+    return c;
+}
+
+// The number of bound vertices a lane compares in count_leaf_window (0 when it
+// counts nothing), maximised over the lanes that run this together.
+template <int S>
+__device__ __forceinline__ uint32_t leaf_compares(bool counting, uint32_t hdr) {
+    const uint32_t nq = counting ? ((hdr >> 8) & 15) - 1u : 0u;
+    uint32_t nqm = 0;
+#pragma unroll
+    for (int k = 1; k < S; ++k) nqm += __ballot(nq >= (uint32_t)k) ? 1u : 0u;
+    return nqm;
+}
+
+// A partial match at level L whose trie node has leaf children only (every
+// match below it is one more edge), counted by the lane that found it, with
+// no level buffer: the lane finds and counts the window of each of the node's
+// groups in turn.  A window longer than p.leaf_scan entries is left to the
+// whole wave, which counts such windows between the lanes' turns.  ph[]: the
+// bound vertices, eid and tp: its last edge and that edge's time, tf: its
+// first time, r1: its root's slot in the level-1 batch (root windows).
+template <typename TT, int D, int MODE, int S>
+__device__ __forceinline__ void count_leaf_parent(const KParams<TT> &p,
+                                                  WaveLds<TT, D, keep_of(MODE)> &W,
+                                                  unsigned long long *cnt, const int lane,
+                                                  bool act, uint32_t node,
+                                                  const int32_t (&ph)[S], uint32_t eid, TT tp,
+                                                  TT tf, uint32_t r1, uint32_t nd) {
+    const uint32_t iw = act ? p.tree.inode[node] : 0u;
+    uint32_t gi = iw & 0xfffffu;
+    const uint32_t gend = gi + (act ? node_groups(iw) : 0u);
+    const TT thi = sat_add(tf, p.delta_sat);
+    for (;;) {
+        bool pend = false;     // a window for the whole wave: group pg, [pl0, pl0 + plen)
+        uint32_t pg = 0, pl0 = 0, plen = 0;
+        while (gi < gend) {
+            const uint32_t g = gi;
+            const uint32_t hdr = p.tree.grp[2 * g].x;
+            const uint32_t dir = hdr & 15, anc = (hdr >> 4) & 15;
+            const Entry<TT> *adj = dir == kDirOut ? p.g.out_adj : p.g.in_adj;
+            const TT *ta = times_of(adj);
+            uint32_t b = 0, e = 0, l0;
+            bool hinted = false;
+            if constexpr (D > 2) {
+                if (anc < 2) {
+                    const uint32_t k = anc * 2u + dir;
+                    const uint32_t hl = W.hlen[k][r1];
+                    hinted = hl != kNoHint;
+                    b = W.hlo[k][r1];
+                    e = b + hl;
+                }
+            }
+            if (!hinted) {
+                int32_t a = ph[0];
+#pragma unroll
+                for (int t = 1; t < S; ++t) a = anc == (uint32_t)t ? ph[t] : a;
+                const uint32_t *off = dir == kDirOut ? p.g.out_off : p.g.in_off;
+                b = off[a];
+                e = off[a + 1];
+            }
+            const uint32_t le = (hdr >> 13) & 3u;
+            if (le) {
+                // the list of an endpoint of the last edge: its rank is kept
+                const uint32_t k = (le == 1 ? 0u : 2u) + (dir == kDirOut ? 0u : 1u);
+                l0 = reinterpret_cast<const uint32_t *>(p.g.gx)[4 * (size_t)eid + k];
+            } else {
+                l0 = first_greater(ta, 1, b, e, tp);
+            }
+            const uint32_t len = (hinted ? e : gallop_greater(ta, 1, l0, e, thi)) - l0;
+            if (len > p.leaf_scan) {
+                pend = true; pg = g; pl0 = l0; plen = len;
+                break;
+            }
+            const uint32_t nqm = leaf_compares<S>(len > 0, hdr);
+            if (len > 0) count_leaf_window<TT, D, MODE>(p, g, hdr, ph, tf, l0, len, nqm, cnt, nd);
+            ++gi;
+        }
+        for (uint64_t cm = __ballot(pend); cm; cm &= cm - 1) {
+            const int src = (int)__builtin_ctzll(cm);
+            int32_t wph[S];
+#pragma unroll
+            for (int t = 0; t < S; ++t) wph[t] = (int32_t)__builtin_amdgcn_readlane(ph[t], src);
+            const uint32_t wg = __builtin_amdgcn_readlane(pg, src);
+            const uint32_t wl0 = __builtin_amdgcn_readlane(pl0, src);
+            const uint32_t wlen = __builtin_amdgcn_readlane(plen, src);
+            if (nd == 1)
+                leaf_scan_wave<TT, S>(p, wph, wg, wl0, wlen, lane, cnt, 1u, 0u);
+            else
+                leaf_scan_wave_multi<TT, S>(p, wph, wg, wl0, wlen,
+                                            lane_time(tf, src), lane, cnt, nd);
+        }
+        if (pend) ++gi;
+        if (!__ballot(gi < gend)) break;
+    }
+}
+
 // per-lane statistics (only the STATS instantiation touches them)
 struct Stats {
     uint64_t v[kStats];
@@ -430,6 +582,40 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, k
     // windows counted at once (MODE 0 serves trees with one window only)
     const uint32_t nd = MODE == 0 ? 1u : (uint32_t)p.tree.n_d;
 
+    if constexpr ((MODE == 0 || MODE == 3) && L > 1 && D <= 4) {
+        // a batch of leaf parents only (every match below is one more edge):
+        // one lane per partial match finds and counts all of its windows
+        // (measured faster for trees of up to four edges, slower for five)
+        if (p.leaf_scan != 0) {
+            bool mixed = false;
+            for (uint32_t x0 = 0; x0 < nA; x0 += kWave) {
+                const uint32_t x = x0 + lane;
+                if (x < nA) mixed = mixed || (inode[A.node[x]] & kLeafParent) == 0;
+            }
+            if (!__ballot(mixed)) {
+                for (uint32_t x0 = 0; x0 < nA; x0 += kWave) {
+                    const uint32_t x = x0 + lane;
+                    const bool act = x < nA;
+                    int32_t ph[SA];
+                    uint32_t node = 0, eid = 0, r1 = 0;
+                    TT tp = 0, tf = 0;
+#pragma unroll
+                    for (int t = 0; t < SA; ++t) ph[t] = act ? vtx(t, x) : -1;
+                    if (act) {
+                        node = A.node[x];
+                        eid = A.eid[x];
+                        tp = p.g.gt[eid];
+                        tf = tfirst_of(x);
+                        r1 = A.r1[x];
+                    }
+                    count_leaf_parent<TT, D, MODE, SA>(p, W, cnt, lane, act, node, ph, eid, tp, tf,
+                                                       r1, nd);
+                }
+                return;
+            }
+        }
+    }
+
 
     // child groups per buffered partial match -> inclusive prefix (at the
     // root level every entry has the root's groups).  Below it the pairs are
@@ -439,7 +625,7 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, k
     // (pairs are numbered over both classes: the first P0 are of the first, so
     // only the pass across the boundary mixes them).
     uint32_t P = 0, P0 = 0, P1 = 0;
-    const uint32_t root_ng = (inode[0] >> 20) & 63u;
+    const uint32_t root_ng = node_groups(inode[0]);
     if constexpr (L == 1) {
         P = nA * root_ng;
     } else {
@@ -448,8 +634,8 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, k
             uint32_t n0 = 0, n1 = 0;
             if (x < nA) {
                 const uint32_t w = inode[A.node[x]];
-                n0 = w >> 26;
-                n1 = ((w >> 20) & 63u) - n0;
+                n0 = node_near(w);
+                n1 = node_groups(w) - n0;
             }
             const uint32_t i0 = incl_scan32(n0, lane) + P0;
             const uint32_t i1 = incl_scan32(n1, lane) + P1;
@@ -497,7 +683,7 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, k
                         }
                         const uint32_t before = lo ? pin[lo - 1] : 0u;
                         const uint32_t w = inode[A.node[lo]];
-                        g = (w & 0xfffffu) + (c1 ? (w >> 26) : 0u) + (pj - before);
+                        g = (w & 0xfffffu) + (c1 ? node_near(w) : 0u) + (pj - before);
                     }
                     x = lo;
                     hdr = grp[2 * g].x;
@@ -593,55 +779,13 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, k
                 const bool leaf = take && len > 0 && p.leaf_scan && ((hdr >> 12) & 1);
                 const bool scanned = leaf && len <= p.leaf_scan;
                 const bool coop = leaf && len > p.leaf_scan;
-                // bound vertices to compare with, the anchor left out; the
-                // count loop is compiled for the wave's largest number
-                const uint32_t nq = scanned && own ? ((hdr >> 8) & 15) - 1u : 0u;
-                uint32_t nqm = 0;
-#pragma unroll
-                for (int k = 1; k < SA; ++k) nqm += __ballot(nq >= (uint32_t)k) ? 1u : 0u;
+                const uint32_t nqm = leaf_compares<SA>(scanned && own, hdr);
                 if (scanned && own) {
-                    constexpr int NQ = SA - 1;
-                    const uint32_t anc = (hdr >> 4) & 15;
-                    const uint4 ga = grp[2 * g], gb = grp[2 * g + 1];
                     int32_t ph[SA];
 #pragma unroll
                     for (int t = 0; t < SA; ++t) ph[t] = vtx(t, x);
-                    const uint32_t words[6] = {ga.y, ga.z, ga.w, gb.x, gb.y, gb.z};
-                    int32_t q[NQ];
-                    uint32_t w[NQ];
-#pragma unroll
-                    for (int i = 0; i < NQ; ++i) {
-                        // slot i below the anchor, slot i + 1 from it on
-                        const bool below = (uint32_t)i < anc, on = (uint32_t)i < nq;
-                        q[i] = on ? (below ? ph[i] : ph[i + 1]) : -1;
-                        w[i] = on ? (below ? words[i] : words[i + 1]) : 0u;
-                    }
-                    const Entry<TT> *adj = (hdr & 15) == kDirOut ? p.g.out_adj : p.g.in_adj;
-                    // loads per step (measured: 8 for trees up to depth 3, 4 deeper)
-                    constexpr int kLU = D <= 3 ? 8 : 4;
-                    auto count = [&](uint32_t n, uint32_t j, bool move) -> uint32_t {
-                        uint32_t c = 0;
-                        if constexpr (NQ >= 1) if (nqm == 1) c = leaf_count<kLU, 1>(adj, l0, n, q, w, gb.w, cnt, nd, j, move);
-                        if constexpr (NQ >= 2) if (nqm == 2) c = leaf_count<kLU, 2>(adj, l0, n, q, w, gb.w, cnt, nd, j, move);
-                        if constexpr (NQ >= 3) if (nqm == 3) c = leaf_count<kLU, 3>(adj, l0, n, q, w, gb.w, cnt, nd, j, move);
-                        if constexpr (NQ >= 4) if (nqm == 4) c = leaf_count<kLU, 4>(adj, l0, n, q, w, gb.w, cnt, nd, j, move);
-                        if constexpr (NQ >= 5) if (nqm == 5) c = leaf_count<kLU, 5>(adj, l0, n, q, w, gb.w, cnt, nd, j, move);
-                        return c;
-                    };
-                    // the whole window counts at the largest window
-                    const uint32_t c = count(len, nd - 1, false);
-                    if constexpr (MODE != 0) {
-                        // each smaller window is a prefix of this one: its
-                        // matches move down one slot (usually it is empty)
-                        const TT *ta = times_of(adj);
-                        const TT tf = tfirst_of(x);
-                        uint32_t e = l0 + len;
-                        for (uint32_t j = nd - 1; j-- > 0;) {
-                            e = gallop_greater(ta, 1, l0, e, sat_add(tf, window_lo(p, j)));
-                            if (e == l0) break;
-                            count(e - l0, j, true);
-                        }
-                    }
+                    const uint32_t c = count_leaf_window<TT, D, MODE>(p, g, hdr, ph, tfirst_of(x),
+                                                                      l0, len, nqm, cnt, nd);
                     if constexpr (STATS) st.v[kStatCredit] += c;
                 }
                 for (uint64_t cm = __ballot(coop && own); cm; cm &= cm - 1) {
