@@ -425,8 +425,8 @@ __device__ __forceinline__ uint32_t count_leaf_window(const KParams<TT> &p, uint
         w[i] = on ? (below ? words[i] : words[i + 1]) : 0u;
     }
     const Entry<TT> *adj = (hdr & 15) == kDirOut ? p.g.out_adj : p.g.in_adj;
-    // loads per step (measured: 8 for trees up to depth 3, 4 deeper)
-    constexpr int kLU = D <= 3 ? 8 : 4;
+    // loads per step (measured: 8 for trees up to depth 4, 4 deeper)
+    constexpr int kLU = D <= 4 ? 8 : 4;
     auto count = [&](uint32_t n, uint32_t j, bool move) -> uint32_t {
         uint32_t c = 0;
         if constexpr (NQ >= 1) if (nqm == 1) c = leaf_count<kLU, 1>(adj, l0, n, q, w, gb.w, cnt, nd, j, move);

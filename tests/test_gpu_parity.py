@@ -106,6 +106,28 @@ def test_medium_graph_all_modes(delta):
     assert np.array_equal(api.count(g, tr, roots=roots), oracle_counts(og, ms, delta, roots))
 
 
+@pytest.mark.parametrize("kmax", [3, 4])
+def test_medium_graph_leaf_parents(kmax):
+    # trees of up to four edges count batches of leaf parents (nodes whose
+    # children all end a motif) one partial match per lane, with groups of
+    # lanes sharing each short window and the whole wave taking long ones
+    s, d, t, n, ms = _medium(seed=2)
+    ms = [m for m in ms if len(m) <= kmax]
+    og = OracleGraph(s, d, t, n)
+    g = api.Graph(s, d, t, n)
+    for delta in (7, 40, 200):
+        want = oracle_counts(og, ms, delta)
+        tr = api.Tree(ms, delta)
+        say("leaf parents", kmax, delta)
+        for blocks, chunk, queues, ls in ((0, 64, 0, 0), (1, 64, 0, 1), (0, 128, 3, 5),
+                                          (0, 64, 8, 17), (2, 192, 1, 1000)):
+            assert np.array_equal(api.count(g, tr, blocks=blocks, chunk=chunk, queues=queues,
+                                            leaf_scan=ls), want), (delta, ls)
+        tm = api.Tree(ms, [3, delta, 2 * delta])
+        want_m = np.stack([oracle_counts(og, ms, x) for x in (3, delta, 2 * delta)])
+        assert np.array_equal(api.count(g, tm), want_m), delta
+
+
 @pytest.mark.parametrize("seed", range(3))
 def test_multi_window_tiny(seed):
     """One search for several windows equals the oracle at every window, on
