@@ -502,9 +502,11 @@ __device__ __forceinline__ void count_leaf_parent(const KParams<TT> &p,
                 }
             }
             if (!hinted) {
-                int32_t a = ph[0];
+                // the anchor's vertex by masks: a select chain over ph[]
+                // would be turned into an indexed load from scratch memory
+                int32_t a = 0;
 #pragma unroll
-                for (int t = 1; t < S; ++t) a = anc == (uint32_t)t ? ph[t] : a;
+                for (int t = 0; t < S; ++t) a |= ph[t] & -(int32_t)(anc == (uint32_t)t);
                 const uint32_t *off = dir == kDirOut ? p.g.out_off : p.g.in_off;
                 b = off[a];
                 e = off[a + 1];
