@@ -244,7 +244,22 @@ __device__ __forceinline__ uint32_t leaf_scan_wave_multi(const KParams<TT> &p,
         thr[j] = sat_add(tf, p.dlo[j]);
         pre[j] = 0;
     }
-    for (uint32_t i = 0; i < len; i += kWave) {
+    // four independent loads per pass while whole, then one at a time
+    uint32_t i = 0;
+    for (; i + 4 * kWave <= len; i += 4 * kWave) {
+        Entry<TT> en[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) en[k] = e[i + k * kWave + lane];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+#pragma unroll
+            for (int s = 0; s < SA; ++s) c[s] += (uint32_t)__popcll(__ballot(en[k].v == q[s]));
+#pragma unroll
+            for (int j = 0; j < kMaxDeltas - 1; ++j)
+                if ((uint32_t)j + 1 < nd) pre[j] += (uint32_t)__popcll(__ballot(en[k].t <= thr[j]));
+        }
+    }
+    for (; i < len; i += kWave) {
         const bool in = i + lane < len;
         Entry<TT> en{};
         if (in) en = e[i + lane];
