@@ -510,12 +510,21 @@ def main():
         roofline["hbm_frac"] = traffic / k_avg_s / 1e9 / HBM_PEAK_GBS
         if rec.get("tcc_hit") is not None:
             roofline["l2_hit"] = rec["tcc_hit"] / (rec["tcc_hit"] + rec["tcc_miss"])
+        # what limits the kernel: the busiest of HBM bandwidth, VALU issue
+        # (counted instructions over the issue rate of 256 CUs) and the vector
+        # memory units (TA address and TD data busy cycles per CU over the
+        # profiled launch)
+        busy = {"HBM bandwidth": roofline["hbm_frac"]}
         if rec.get("valu_insts") is not None:
-            # what limits the kernel: VALU issue (counted instructions over the
-            # issue rate of 256 CUs), not HBM bandwidth
-            roofline["limiter"] = "VALU issue"
             roofline["valu_insts"] = rec["valu_insts"]
             roofline["valu_issue_frac"] = rec["valu_insts"] / VALU_PEAK_INSTS_PER_S / k_avg_s
+            busy["VALU issue"] = roofline["valu_issue_frac"]
+        for key, name in (("ta_busy_frac", "vector memory addressing (TA)"),
+                          ("td_busy_frac", "vector memory data return (TD)")):
+            if rec.get(key) is not None:
+                roofline[key] = rec[key]
+                busy[name] = rec[key]
+        roofline["limiter"] = max(busy, key=busy.get)
     out = {
         "metric": "root edges searched/s + co-mine speedup vs per-motif on GPU, exact counts",
         "value": value,
