@@ -201,6 +201,21 @@ typedef struct {
                                  waves not launched are 0.  For measuring how
                                  evenly a schedule ends; counts are unchanged. */
     int64_t wave_clock_len;
+    /* Epochs (paper, section 4.5: inter-warp load balancing).  With
+     * epoch_idle > 0, a launch ends its epoch once that percentage of its
+     * waves has run out of work: the waves still searching write what is left
+     * of their root-level windows as contexts (root edge, group, a range of
+     * at most 64 candidates), finish the deeper work they already hold and
+     * exit.  The next launch spreads those contexts over all of its waves, and
+     * so on until no context is left; the last of max_epochs launches runs to
+     * the end.  A context's candidates are never searched twice, so counts
+     * are exact.  MG_MODE_COMINE with MG_SCHED_PLAIN only, and not with stop,
+     * max_chunks, cursor, stats, root_cost or wave_clock (MG_EINVAL). */
+    int32_t epoch_idle;       /* 0 = off, else 1..100 (percent of the waves) */
+    int32_t max_epochs;       /* launches at most; 0 = default (16) */
+    int64_t *epoch_contexts;  /* optional out, max_epochs entries: contexts
+                                 carried out of each launch (0 from the last
+                                 one on) */
 } mg_count_opts;
 
 /* Resume point of a stopped count.  Initialise with mg_cursor_init; pass the

@@ -60,7 +60,8 @@ class CountOpts(ctypes.Structure):
                 ("root_cost", ctypes.c_void_p), ("sample", ctypes.c_int32),
                 ("stop", ctypes.c_void_p), ("max_chunks", ctypes.c_int64),
                 ("cursor", ctypes.c_void_p), ("wave_clock", ctypes.c_void_p),
-                ("wave_clock_len", ctypes.c_int64)]
+                ("wave_clock_len", ctypes.c_int64), ("epoch_idle", ctypes.c_int32),
+                ("max_epochs", ctypes.c_int32), ("epoch_contexts", ctypes.c_void_p)]
 
 
 class TuneResult(ctypes.Structure):
@@ -336,7 +337,8 @@ class Tree:
 
 def count(graph: Graph, tree: Tree, mode="comine", roots=None, blocks=0, chunk=0,
           queues=0, stream=None, timed=False, stats=False, root_cost=False, model=None,
-          leaf_scan=0, sample=0, stop=None, max_chunks=0, cursor=None, wave_clock=None):
+          leaf_scan=0, sample=0, stop=None, max_chunks=0, cursor=None, wave_clock=None,
+          epoch_idle=0, max_epochs=0, epoch_contexts=None):
     """Exact count per motif (``mg_count``), in the tree's motif order.
 
     ``mode``: "comine" (one search over the MG-Tree) or "per_motif" (one search
@@ -350,7 +352,11 @@ def count(graph: Graph, tree: Tree, mode="comine", roots=None, blocks=0, chunk=0
     ``max_chunks`` and ``cursor`` (a ``Cursor``, updated in place) stop a
     count early and resume it; the counts are then those of this call.
     ``wave_clock`` (a uint64 array, filled in place) receives every wave's
-    start and end ticks.
+    start and end ticks.  ``epoch_idle`` (percent of the waves) turns on
+    epochs: a launch ends once that many waves are idle and the next one
+    spreads the root-level candidates left over across all waves;
+    ``max_epochs`` bounds the launches and ``epoch_contexts`` (an int64 array
+    of that length, filled in place) receives the contexts each one left.
     """
     L = lib()
     o = CountOpts()
@@ -374,6 +380,12 @@ def count(graph: Graph, tree: Tree, mode="comine", roots=None, blocks=0, chunk=0
         assert wave_clock.dtype == np.uint64 and wave_clock.flags.c_contiguous
         o.wave_clock = wave_clock.ctypes.data
         o.wave_clock_len = wave_clock.size
+    o.epoch_idle = int(epoch_idle)
+    o.max_epochs = int(max_epochs)
+    if epoch_contexts is not None:
+        assert epoch_contexts.dtype == np.int64 and epoch_contexts.flags.c_contiguous
+        assert epoch_contexts.size >= (max_epochs if max_epochs > 0 else 16)
+        o.epoch_contexts = epoch_contexts.ctypes.data
     r = None
     if roots is not None:
         r = np.ascontiguousarray(roots, dtype=np.int64)

@@ -95,6 +95,17 @@ struct DevGraph {
     uint32_t n_edges;
 };
 
+// A piece of search left over when an epoch ends: the candidates of one
+// root-level window, entries [e0, e1) of the list of group g of the root
+// a -> b at time t_lo | t_hi << 32.  The root itself was credited when it was
+// started.
+struct EpochCtx {
+    int32_t a, b;
+    uint32_t t_lo, t_hi;
+    uint32_t g, e0, e1, pad;
+};
+constexpr uint32_t kCtxPiece = 64;   // candidates per context at most
+
 template <typename TT>
 struct KParams {
     DevGraph<TT> g;
@@ -132,6 +143,21 @@ struct KParams {
     unsigned long long *wave_clock;  // NULL, or per wave: start and end of its search
                                      // (device real-time clock ticks)
     uint32_t n_wave_clock;           // waves that wave_clock holds
+    // epochs (MODE 0 and 3): ctx_out NULL = off.  A wave that finds no work
+    // left adds one to *idle; once *idle reaches idle_pct percent of the
+    // launch's waves, the waves still searching stop expanding root-level
+    // candidates, write what is left of their root-level windows as contexts,
+    // finish what they already hold and exit.  The next launch searches the
+    // contexts (ctx_in) instead of the root queues, claiming them through the
+    // item slot of `queues`.
+    EpochCtx *ctx_out;            // contexts written (ctx_cap at most)
+    unsigned long long *ctx_count;  // contexts written so far (zeroed)
+    unsigned long long ctx_cap;
+    uint32_t *idle;               // idle waves (zeroed)
+    uint32_t idle_pct;            // the epoch ends once this percentage of the
+                                  // launch's waves is idle (1..100)
+    const EpochCtx *ctx_in;       // NULL, or the contexts this launch searches
+    uint32_t n_ctx_in;
     uint32_t leaf_scan;           // windows whose children are all leaves are counted
                                   // without the candidate expansion: by one lane up
                                   // to this long, by the whole wave when longer

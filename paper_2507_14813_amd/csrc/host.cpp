@@ -465,6 +465,57 @@ void fill_params(mg::KParams<TT> &p, const mg_graph *g, const mg_tree *tr, const
     p.max_chunks = (uint32_t)o.max_chunks;
 }
 
+// Epochs (paper, section 4.5): launch after launch, each ending once
+// o.epoch_idle percent of its waves are idle; the root-level candidates the
+// busy waves had not reached yet come back as contexts, which the next launch
+// spreads over all of its waves.  The last of max_epochs launches runs to the
+// end.  Counts accumulate in p.counts; p.queues is cleared before each launch.
+constexpr uint64_t kCtxCap = 1u << 21;   // contexts one epoch can hand on
+
+template <typename TT>
+int epoch_search(mg::KParams<TT> p, const mg_count_opts &o, hipStream_t st) {
+    const int max_epochs = o.max_epochs > 0 ? o.max_epochs : 16;
+    struct Free {
+        DevBuf *b;
+        ~Free() { dev_free(b[0]); dev_free(b[1]); dev_free(b[2]); }
+    };
+    DevBuf all[3];
+    Free fr{all};
+    for (int i = 0; i < 2; ++i) {
+        int rc = dev_alloc(all[i], sizeof(mg::EpochCtx) * kCtxCap, (void *)st);
+        if (rc) return rc;
+    }
+    int rc = dev_alloc(all[2], 16, (void *)st);
+    if (rc) return rc;
+    p.ctx_count = (unsigned long long *)all[2].ptr;
+    p.idle = (uint32_t *)((char *)all[2].ptr + 8);
+    p.ctx_cap = kCtxCap;
+    p.idle_pct = (uint32_t)o.epoch_idle;
+    for (int ep = 0; ep < max_epochs; ++ep) {
+        const bool last = ep + 1 == max_epochs;
+        p.ctx_out = last ? nullptr : (mg::EpochCtx *)all[ep & 1].ptr;
+        HIP_TRY(hipMemsetAsync(all[2].ptr, 0, 16, st));
+        if (ep > 0) HIP_TRY(hipMemsetAsync(p.queues, 0, kQueueBytes, st));
+        // (the first launch with neither contexts in nor out is the plain search)
+        hipError_t e = mg::launch_comine<TT>(p, o.blocks, st);
+        if (e != hipSuccess)
+            return fail(MG_EDEVICE, "co-mining launch failed: %s", hipGetErrorString(e));
+        unsigned long long n = 0;
+        if (p.ctx_out) {
+            HIP_TRY(hipMemcpyAsync(&n, p.ctx_count, sizeof n, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+        }
+        if (o.epoch_contexts) o.epoch_contexts[ep] = (int64_t)n;
+        if (n == 0) {
+            for (int k = ep + 1; o.epoch_contexts && k < max_epochs; ++k) o.epoch_contexts[k] = 0;
+            break;
+        }
+        p.ctx_in = (const mg::EpochCtx *)all[ep & 1].ptr;
+        p.n_ctx_in = (uint32_t)n;
+    }
+    return MG_OK;
+}
+
 template <typename TT>
 int launch_tree(const mg_graph *g, mg_tree *tr, const uint32_t *d_roots, uint32_t n_roots,
                 unsigned long long *d_queues, unsigned long long *d_counts,
@@ -497,6 +548,9 @@ int launch_tree(const mg_graph *g, mg_tree *tr, const uint32_t *d_roots, uint32_
     if (n_roots > 0 && o.sched == MG_SCHED_LEARNED) {
         int rc = learned_search<TT>(g, tr, o.model, p, o.blocks,
                                     o.sample > 0 ? (uint32_t)o.sample : kSampleDefault, st);
+        if (rc) return rc;
+    } else if (n_roots > 0 && o.epoch_idle > 0) {
+        int rc = epoch_search<TT>(p, o, st);
         if (rc) return rc;
     } else if (n_roots > 0) {
         hipError_t e = mg::launch_comine<TT>(p, o.blocks, st);
@@ -1440,9 +1494,10 @@ int mg_count_noalloc(const mg_graph *g, const mg_tree *tr, const mg_count_opts *
         mg_count_opts_init(&o);
         if (opts) o = *opts;
         if (o.mode != MG_MODE_COMINE || o.sched != MG_SCHED_PLAIN || o.roots || o.root_cost ||
-            o.elapsed_ms || o.cursor || o.wave_clock)
+            o.elapsed_ms || o.cursor || o.wave_clock || o.epoch_idle)
             return fail(MG_EINVAL, "mg_count_noalloc takes co-mining with the plain schedule over "
-                                   "every root; roots, root_cost, elapsed_ms and cursor need memory");
+                                   "every root; roots, root_cost, elapsed_ms, cursor and epochs "
+                                   "need memory");
         if (o.chunk < 0 || (o.chunk % 64) != 0 || o.chunk > (1 << 16))
             return fail(MG_EINVAL, "chunk must be a multiple of 64 in [0, 65536]");
         if (o.queues < 0 || o.queues > mg::kQueues)
@@ -1540,6 +1595,12 @@ int mg_count(const mg_graph *g, const mg_tree *tr_c, const mg_count_opts *opts,
         const bool stoppable = o.stop || o.max_chunks || o.cursor;
         if (stoppable && (o.mode != MG_MODE_COMINE || o.sched != MG_SCHED_PLAIN))
             return fail(MG_EINVAL, "stop, max_chunks and cursor need co-mining with the plain schedule");
+        if (o.epoch_idle < 0 || o.epoch_idle > 100 || o.max_epochs < 0)
+            return fail(MG_EINVAL, "epoch_idle must be in [0, 100] and max_epochs >= 0");
+        if (o.epoch_idle && (o.mode != MG_MODE_COMINE || o.sched != MG_SCHED_PLAIN || stoppable ||
+                             o.stats || o.root_cost || o.wave_clock))
+            return fail(MG_EINVAL, "epochs need co-mining with the plain schedule, without stop, "
+                                   "max_chunks, cursor, stats, root_cost or wave_clock");
         if (o.cursor && o.cursor->started) {
             const int32_t ch = o.chunk > 0 ? o.chunk : 64, nq = o.queues > 0 ? o.queues : mg::kQueues;
             const int64_t nr = o.roots ? o.n_roots : g->E;

@@ -376,6 +376,10 @@ __device__ __forceinline__ LevelBuf<TT, L, R> &lvl(LevelChain<TT, D, R, M> &c) {
 // What the level buffers keep per partial match beyond the search itself
 // (the R of LevelBuf) in each kernel MODE.
 constexpr int keep_of(int mode) { return mode == 2 ? 1 : mode == 4 ? 2 : 0; }
+// MODE 5 and 6 are MODE 0 and 3 with epochs (context offload, KParams::ctx_*)
+constexpr bool single_of(int mode) { return mode == 0 || mode == 5; }   // one window
+constexpr bool plain_of(int mode) { return mode == 0 || mode == 3 || mode == 5 || mode == 6; }
+constexpr bool epochs_of(int mode) { return mode == 5 || mode == 6; }
 
 // Enumeration: the edge ids of partial match i at level L, first edge first,
 // into e[0..L), following the parent slots up to the root batch.
@@ -453,7 +457,7 @@ __device__ __forceinline__ uint32_t count_leaf_window(const KParams<TT> &p, uint
     };
     // the whole window counts at the largest window
     const uint32_t c = count(len, nd - 1, false);
-    if constexpr (MODE != 0) {
+    if constexpr (!single_of(MODE)) {
         // each smaller window is a prefix of this one: its matches move down
         // one slot (usually it is empty)
         const TT *ta = times_of(adj);
@@ -565,11 +569,12 @@ __device__ __forceinline__ void count_leaf_parent(const KParams<TT> &p,
 // per-lane statistics (only the STATS instantiation touches them)
 struct Stats {
     uint64_t v[kStats];
+    bool dumped;   // the wave wrote contexts (an epoch ended): claim no more work
 };
 
 // MODE: 0 plain search (trees with one window), 1 with search statistics, 2
 // with the per-root cost log, 3 plain search of a tree with several windows,
-// 4 enumeration (every match written out)
+// 4 enumeration (every match written out), 5 and 6: 0 and 3 with epochs
 // At level 1 with nparts > 1 (one buffered root), only part `part` of the
 // root's candidates is expanded: [T * part / nparts, T * (part + 1) / nparts)
 // of its T candidates in window order, so that the parts of one root
@@ -579,7 +584,8 @@ template <typename TT, int D, int MODE, int L>
 __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, keep_of(MODE)> &W,
                                           unsigned long long *cnt, const int lane,
                                           const uint32_t nA, Stats &st, const uint32_t part = 0,
-                                          const uint32_t nparts = 1) {
+                                          const uint32_t nparts = 1,
+                                          const EpochCtx *ctx = nullptr) {
     constexpr bool STATS = MODE == 1, LOG = MODE == 2;
     LevelBuf<TT, L, keep_of(MODE)> &A = lvl<L>(W.lv);
     constexpr int SA = LevelBuf<TT, L, keep_of(MODE)>::S;
@@ -597,9 +603,9 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, k
     const uint4 *__restrict__ grp = p.tree.grp;
     const uint64_t le_mask = (lane == 63) ? ~0ull : ((2ull << lane) - 1);
     // windows counted at once (MODE 0 serves trees with one window only)
-    const uint32_t nd = MODE == 0 ? 1u : (uint32_t)p.tree.n_d;
+    const uint32_t nd = single_of(MODE) ? 1u : (uint32_t)p.tree.n_d;
 
-    if constexpr ((MODE == 0 || MODE == 3) && L > 1 && D <= 4) {
+    if constexpr (plain_of(MODE) && L > 1 && D <= 4) {
         // a batch of leaf parents only (every match below is one more edge):
         // one lane per partial match finds and counts all of its windows
         // (measured faster for trees of up to four edges, slower for five)
@@ -644,7 +650,7 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, k
     uint32_t P = 0, P0 = 0, P1 = 0;
     const uint32_t root_ng = node_groups(inode[0]);
     if constexpr (L == 1) {
-        P = nA * root_ng;
+        P = ctx ? nA : nA * root_ng;   // a context is one window of its root
     } else {
         for (uint32_t x0 = 0; x0 < nA; x0 += kWave) {
             const uint32_t x = x0 + lane;
@@ -672,9 +678,21 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, k
     uint4 wrec = make_uint4(0, 0, 0, 0);
     uint32_t pc = 0, nw = 0, T = 0, cc = 0;
     uint32_t nB = 0;   // partial matches buffered at level L+1
+    // epochs: root-level candidates are written out as contexts instead of
+    // expanded once enough waves are idle (polled every 16 passes)
+    bool dumping = false, room = true;
+    uint32_t polls = 0;
 
     for (;;) {
         bool done = false;
+        if constexpr (L == 1 && epochs_of(MODE)) {
+            if (p.ctx_out && room && !dumping && (++polls & 15u) == 0) {
+                uint32_t v = 0;
+                if (lane == 0) v = __hip_atomic_load(p.idle, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t waves = gridDim.x * (uint32_t)kWavesPerBlock;
+                dumping = (uint64_t)lane_value(v, 0) * 100u >= (uint64_t)p.idle_pct * waves;
+            }
+        }
         if (cc >= T) {
             if (pc >= P) {
                 done = true;
@@ -685,9 +703,19 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, k
                 bool all = false;
                 if (pi < P) {
                     uint32_t lo = 0;
+                    bool given = false;   // the window comes with a context
                     if constexpr (L == 1) {
-                        lo = pi / root_ng;
-                        g = (inode[0] & 0xfffffu) + (pi - lo * root_ng);
+                        if (ctx) {
+                            const EpochCtx c = ctx[pi];
+                            lo = pi;
+                            g = c.g;
+                            l0 = c.e0;
+                            len = c.e1 - c.e0;
+                            given = true;
+                        } else {
+                            lo = pi / root_ng;
+                            g = (inode[0] & 0xfffffu) + (pi - lo * root_ng);
+                        }
                     } else {
                         const bool c1 = pi >= P0;   // second class
                         const uint32_t pj = c1 ? pi - P0 : pi;
@@ -704,67 +732,71 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, k
                     }
                     x = lo;
                     hdr = grp[2 * g].x;
-                    const int dir = hdr & 15, anc = (hdr >> 4) & 15;
-                    const TT thi = sat_add(tfirst_of(lo), p.delta_sat);
-                    uint32_t b, e, sh;
-                    const TT *ta;
-                    bool hinted = false, known = false;
-                    if (dir == kDirAll) {
-                        b = 0; e = p.g.n_edges; ta = p.g.gt; sh = 0;
-                        all = true;
-                        if constexpr (L > 1) {
-                            // the whole-list window starts after the last edge
-                            // itself (past the entries with its time)
-                            b = A.eid[lo] + 1u;
-                        }
+                    if (given) {
+                        all = (hdr & 15) == kDirAll;
                     } else {
-                        ta = times_of(dir == kDirOut ? p.g.out_adj : p.g.in_adj);
-                        sh = 1;
-                        if constexpr (L > 1 && D > 2) {
-                            if (anc < 2) {
-                                const uint32_t k = (uint32_t)anc * 2u + (uint32_t)dir;
-                                const uint32_t r1 = A.r1[lo];
-                                const uint32_t hl = W.hlen[k][r1];
-                                hinted = hl != kNoHint;
-                                b = W.hlo[k][r1];
-                                e = b + hl;
+                        const int dir = hdr & 15, anc = (hdr >> 4) & 15;
+                        const TT thi = sat_add(tfirst_of(lo), p.delta_sat);
+                        uint32_t b, e, sh;
+                        const TT *ta;
+                        bool hinted = false, known = false;
+                        if (dir == kDirAll) {
+                            b = 0; e = p.g.n_edges; ta = p.g.gt; sh = 0;
+                            all = true;
+                            if constexpr (L > 1) {
+                                // the whole-list window starts after the last edge
+                                // itself (past the entries with its time)
+                                b = A.eid[lo] + 1u;
                             }
-                        }
-                        if (!hinted) {
-                            const int32_t a = vtx((uint32_t)anc, lo);
-                            const uint32_t *off = dir == kDirOut ? p.g.out_off : p.g.in_off;
-                            b = off[a]; e = off[a + 1];
-                        }
-                        if constexpr (L == 1) {
-                            // the root edge's own entries: its windows start at
-                            // the first entry after its time (set with the root)
-                            l0 = W.hlo[(uint32_t)anc * 2u + (uint32_t)dir][lo];
-                            known = true;
                         } else {
-                            // an anchor on the last matched edge: the window
-                            // starts where that edge's time ends in its list
-                            const uint32_t le = (hdr >> 13) & 3u;
-                            if (le) {
-                                const uint4 gx = p.g.gx[A.eid[lo]];
-                                l0 = le == 1 ? (dir == kDirOut ? gx.x : gx.y)
-                                             : (dir == kDirOut ? gx.z : gx.w);
+                            ta = times_of(dir == kDirOut ? p.g.out_adj : p.g.in_adj);
+                            sh = 1;
+                            if constexpr (L > 1 && D > 2) {
+                                if (anc < 2) {
+                                    const uint32_t k = (uint32_t)anc * 2u + (uint32_t)dir;
+                                    const uint32_t r1 = A.r1[lo];
+                                    const uint32_t hl = W.hlen[k][r1];
+                                    hinted = hl != kNoHint;
+                                    b = W.hlo[k][r1];
+                                    e = b + hl;
+                                }
+                            }
+                            if (!hinted) {
+                                const int32_t a = vtx((uint32_t)anc, lo);
+                                const uint32_t *off = dir == kDirOut ? p.g.out_off : p.g.in_off;
+                                b = off[a]; e = off[a + 1];
+                            }
+                            if constexpr (L == 1) {
+                                // the root edge's own entries: its windows start at
+                                // the first entry after its time (set with the root)
+                                l0 = W.hlo[(uint32_t)anc * 2u + (uint32_t)dir][lo];
                                 known = true;
+                            } else {
+                                // an anchor on the last matched edge: the window
+                                // starts where that edge's time ends in its list
+                                const uint32_t le = (hdr >> 13) & 3u;
+                                if (le) {
+                                    const uint4 gx = p.g.gx[A.eid[lo]];
+                                    l0 = le == 1 ? (dir == kDirOut ? gx.x : gx.y)
+                                                 : (dir == kDirOut ? gx.z : gx.w);
+                                    known = true;
+                                }
                             }
                         }
-                    }
-                    if (!known) {
-                        TT tp;
-                        if constexpr (L == 1) tp = A.tfirst[lo];
-                        else tp = p.g.gt[A.eid[lo]];
-                        l0 = all && L > 1 ? gallop_greater(ta, sh, b, e, tp)
-                                          : first_greater(ta, sh, b, e, tp);
-                    }
-                    len = (hinted ? e : gallop_greater(ta, sh, l0, e, thi)) - l0;
-                    if constexpr (L == 1 && D > 2) {
-                        if (!all && anc < 2) {
-                            const uint32_t k = (uint32_t)anc * 2u + (uint32_t)dir;
-                            W.hlo[k][lo] = l0;
-                            W.hlen[k][lo] = len < kNoHint ? (uint16_t)len : kNoHint;
+                        if (!known) {
+                            TT tp;
+                            if constexpr (L == 1) tp = A.tfirst[lo];
+                            else tp = p.g.gt[A.eid[lo]];
+                            l0 = all && L > 1 ? gallop_greater(ta, sh, b, e, tp)
+                                              : first_greater(ta, sh, b, e, tp);
+                        }
+                        len = (hinted ? e : gallop_greater(ta, sh, l0, e, thi)) - l0;
+                        if constexpr (L == 1 && D > 2) {
+                            if (!all && anc < 2) {
+                                const uint32_t k = (uint32_t)anc * 2u + (uint32_t)dir;
+                                W.hlo[k][lo] = l0;
+                                W.hlen[k][lo] = len < kNoHint ? (uint16_t)len : kNoHint;
+                            }
                         }
                     }
                 }
@@ -849,6 +881,62 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, k
                     // one root, so every window fits this one chunk
                     cc = (uint32_t)(((uint64_t)T * part) / nparts);
                     T = (uint32_t)(((uint64_t)T * (part + 1)) / nparts);
+                }
+            }
+        }
+        if constexpr (L == 1 && epochs_of(MODE)) {
+            if (!done && cc < T && dumping) {
+                // write what is left of this chunk's windows as contexts of at
+                // most kCtxPiece candidates each (candidates [cc, T) in window
+                // order; lane w < nw holds window w)
+                uint32_t c_lo = 0, c_hi = 0;
+                if ((uint32_t)lane < nw) {
+                    c_lo = max(cc, wrec.z);
+                    c_hi = wrec.w;
+                }
+                const uint32_t n = c_hi > c_lo ? (c_hi - c_lo + kCtxPiece - 1) / kCtxPiece : 0u;
+                const uint32_t incl = incl_scan32(n, lane);
+                const uint32_t tot = lane_value(incl, kWave - 1);
+                unsigned long long base = 0;
+                uint32_t fits = 1;
+                if (lane == 0) {
+                    // take tot slots, only if all of them fit
+                    unsigned long long old =
+                        __hip_atomic_load(p.ctx_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    for (;;) {
+                        if (old + tot > p.ctx_cap) { fits = 0; break; }
+                        if (__hip_atomic_compare_exchange_strong(p.ctx_count, &old, old + tot,
+                                                                 __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT))
+                            break;
+                    }
+                    base = old;
+                }
+                base = lane0_u64(base);
+                if (lane_value(fits, 0)) {
+                    if (n) {
+                        const uint32_t ox = wrec.x & 255, og = wrec.x >> 8;
+                        const uint64_t tf = (uint64_t)tfirst_of(ox);
+                        EpochCtx c;
+                        c.a = vtx(0, ox);
+                        c.b = vtx(1, ox);
+                        c.t_lo = (uint32_t)tf;
+                        c.t_hi = (uint32_t)(tf >> 32);
+                        c.g = og;
+                        c.pad = 0;
+                        const unsigned long long slot = base + (incl - n);
+                        for (uint32_t k = 0; k < n; ++k) {
+                            const uint32_t c0 = c_lo + k * kCtxPiece;
+                            const uint32_t c1 = min(c0 + kCtxPiece, c_hi);
+                            c.e0 = wrec.y + (c0 - wrec.z);
+                            c.e1 = wrec.y + (c1 - wrec.z);
+                            p.ctx_out[slot + k] = c;
+                        }
+                    }
+                    cc = T;
+                } else {
+                    dumping = false;   // no room left: this wave searches on
+                    room = false;
                 }
             }
         }
@@ -969,6 +1057,9 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, k
         }
         if (done) break;
     }
+    if constexpr (L == 1) {
+        if (dumping) st.dumped = true;
+    }
 }
 
 // Search from part `part` of `nparts` of the root at position r (an edge id:
@@ -1057,13 +1148,42 @@ __device__ __forceinline__ void process_roots(const KParams<TT> &p,
     }
 }
 
+// Search contexts [base, end) of p.ctx_in (at most 64): each becomes a
+// root in the level-1 batch, with its window given (its hints stay unknown:
+// deeper windows of the root's vertices are searched in the whole list).
+template <typename TT, int D, int MODE>
+__device__ __forceinline__ void process_contexts(const KParams<TT> &p,
+                                                 WaveLds<TT, D, keep_of(MODE)> &W,
+                                                 unsigned long long *cnt, const int lane,
+                                                 const uint32_t base, const uint32_t end,
+                                                 Stats &st) {
+    if constexpr (D > 1) {
+        LevelBuf<TT, 1, keep_of(MODE)> &A = lvl<1>(W.lv);
+        const uint32_t i = base + (uint32_t)lane;
+        if (i < end) {
+            const EpochCtx c = p.ctx_in[i];
+            A.phi[0][lane] = c.a;
+            A.phi[1][lane] = c.b;
+            A.tfirst[lane] = (TT)(((uint64_t)c.t_hi << 32) | c.t_lo);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                W.hlo[k][lane] = 0;
+                W.hlen[k][lane] = kNoHint;
+            }
+        }
+        wave_sync();
+        run_level<TT, D, MODE, 1>(p, W, cnt, lane, end - base, st, 0, 1, p.ctx_in + base);
+        wave_sync();
+    }
+}
+
 // Up to depth 3 the plain search (MODE 0) fits 8 waves per SIMD (at most 64
 // VGPRs and 96 SGPRs) without spilling in its loops, and the multi-window
 // search (MODE 3) is faster there with a few spills than at 6 waves; the
 // compiler is asked for that.  Deeper trees and the instrumented modes keep
 // the compiler's own allocation.
 template <int D, int MODE>
-constexpr int min_waves_per_eu() { return D <= 3 && (MODE == 0 || MODE == 3) ? 8 : 1; }
+constexpr int min_waves_per_eu() { return D <= 3 && plain_of(MODE) ? 8 : 1; }
 
 template <typename TT, int D, int MODE>
 __global__ void __launch_bounds__(kWave * kWavesPerBlock)
@@ -1084,6 +1204,7 @@ comine_kernel(const KParams<TT> p) {
     Stats st;
 #pragma unroll
     for (int i = 0; i < kStats; ++i) st.v[i] = 0;
+    st.dumped = false;
     // when each wave starts and ends its search (device real-time clock)
     const uint32_t clock_slot = blockIdx.x * kWavesPerBlock + (uint32_t)wave;
     if (p.wave_clock && lane == 0 && clock_slot < p.n_wave_clock)
@@ -1106,46 +1227,70 @@ comine_kernel(const KParams<TT> p) {
                 process_roots<TT, D, MODE>(p, W, cnt, lane, uniform(item.x), iy, st);
         }
     }
-    // workgroups are dispatched to the XCDs round-robin: start on this XCD's
-    // share of the roots, then take what is left of the others.  A chunk once
-    // claimed is always searched to the end, so after a stop the queue heads
-    // (clamped to the queue lengths) mark exactly the roots searched.
-    const uint32_t nq = p.n_queues;
-    const uint32_t home = blockIdx.x % nq;
-    bool stopped = false;
-    for (uint32_t qi = 0; qi < nq && !stopped; ++qi) {
-        const uint32_t q = (home + qi) % nq;
-        const uint32_t qbeg = queue_begin(p.n_roots, nq, q);
-        const uint32_t qend = queue_end(p.n_roots, nq, q);
-        for (;;) {
-            unsigned long long got = 0;
-            if (lane == 0) {
-                unsigned long long *head = &p.queues[q * kQueueStride];
-                if (p.stop && __hip_atomic_load(p.stop, __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_SYSTEM) != 0) {
-                    got = ~0ull;
-                } else if (p.max_chunks) {
-                    // the budget is spent only on a queue that still has roots,
-                    // so a call makes progress while any root is left: a
-                    // budget holder's claim fails only when another holder
-                    // took the last chunk
-                    const unsigned long long h =
-                        __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if (h >= (unsigned long long)(qend - qbeg)) got = h;
-                    else if (atomicAdd(&p.queues[kBudgetSlot * kQueueStride], 1ull) >= p.max_chunks)
-                        got = ~0ull;
-                    else got = atomicAdd(head, (unsigned long long)p.chunk);
-                } else {
-                    got = atomicAdd(head, (unsigned long long)p.chunk);
-                }
+    bool from_ctx = false;
+    if constexpr (epochs_of(MODE)) {
+        if (p.ctx_in) {
+            // a later epoch: the contexts the last one left, 64 at a time
+            from_ctx = true;
+            for (;;) {
+                unsigned long long it = 0;
+                if (lane == 0) it = atomicAdd(&p.queues[kItemSlot * kQueueStride], (unsigned long long)kWave);
+                it = lane0_u64(it);
+                if (it >= p.n_ctx_in) break;
+                const uint32_t b0 = uniform((uint32_t)it);
+                process_contexts<TT, D, MODE>(p, W, cnt, lane, b0, min(b0 + (uint32_t)kWave, p.n_ctx_in), st);
+                if (st.dumped) break;
             }
-            got = lane0_u64(got);
-            if (got == ~0ull) { stopped = true; break; }
-            if (got >= (unsigned long long)(qend - qbeg)) break;
-            const uint32_t base = uniform(qbeg + (uint32_t)got);
-            if (p.skip && p.skip[base / kWave]) continue;   // searched as an item
-            process_roots<TT, D, MODE>(p, W, cnt, lane, base, min(base + p.chunk, qend), st);
         }
+    }
+    if (!from_ctx) {
+        // workgroups are dispatched to the XCDs round-robin: start on this XCD's
+        // share of the roots, then take what is left of the others.  A chunk once
+        // claimed is always searched to the end, so after a stop the queue heads
+        // (clamped to the queue lengths) mark exactly the roots searched.
+        const uint32_t nq = p.n_queues;
+        const uint32_t home = blockIdx.x % nq;
+        bool stopped = false;
+        for (uint32_t qi = 0; qi < nq && !stopped; ++qi) {
+            const uint32_t q = (home + qi) % nq;
+            const uint32_t qbeg = queue_begin(p.n_roots, nq, q);
+            const uint32_t qend = queue_end(p.n_roots, nq, q);
+            for (;;) {
+                unsigned long long got = 0;
+                if (lane == 0) {
+                    unsigned long long *head = &p.queues[q * kQueueStride];
+                    if (p.stop && __hip_atomic_load(p.stop, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_SYSTEM) != 0) {
+                        got = ~0ull;
+                    } else if (p.max_chunks) {
+                        // the budget is spent only on a queue that still has roots,
+                        // so a call makes progress while any root is left: a
+                        // budget holder's claim fails only when another holder
+                        // took the last chunk
+                        const unsigned long long h =
+                            __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (h >= (unsigned long long)(qend - qbeg)) got = h;
+                        else if (atomicAdd(&p.queues[kBudgetSlot * kQueueStride], 1ull) >= p.max_chunks)
+                            got = ~0ull;
+                        else got = atomicAdd(head, (unsigned long long)p.chunk);
+                    } else {
+                        got = atomicAdd(head, (unsigned long long)p.chunk);
+                    }
+                }
+                got = lane0_u64(got);
+                if (got == ~0ull) { stopped = true; break; }
+                if (got >= (unsigned long long)(qend - qbeg)) break;
+                const uint32_t base = uniform(qbeg + (uint32_t)got);
+                if (p.skip && p.skip[base / kWave]) continue;   // searched as an item
+                process_roots<TT, D, MODE>(p, W, cnt, lane, base, min(base + p.chunk, qend), st);
+                if (st.dumped) { stopped = true; break; }   // an epoch ended
+            }
+        }
+
+    }
+    if constexpr (epochs_of(MODE)) {
+        // out of work: an idle wave, for the epoch limit
+        if (p.ctx_out && !st.dumped && lane == 0) atomicAdd(p.idle, 1u);
     }
 
     if (p.wave_clock && lane == 0 && clock_slot < p.n_wave_clock)
@@ -1175,6 +1320,7 @@ batch_kernel(const BatchParams<TT> bp) {
     WaveLds<TT, D, 0> &W = *reinterpret_cast<WaveLds<TT, D, 0> *>(mine + cnt_bytes);
     W.flag[lane] = 0;
     Stats st;
+    st.dumped = false;
     for (;;) {
         unsigned long long it = 0;
         if (lane == 0) it = atomicAdd(bp.cursor, 1ull);
@@ -1244,6 +1390,8 @@ hipError_t launch_ds(const KParams<TT> &p, int blocks, hipStream_t stream) {
 
 template <typename TT, int D>
 hipError_t launch_d(const KParams<TT> &p, int blocks, hipStream_t stream) {
+    if (p.ctx_in || p.ctx_out)
+        return p.tree.n_d > 1 ? launch_ds<TT, D, 6>(p, blocks, stream) : launch_ds<TT, D, 5>(p, blocks, stream);
     if (p.enum_out) return launch_ds<TT, D, 4>(p, blocks, stream);
     if (p.stats) return launch_ds<TT, D, 1>(p, blocks, stream);
     if (p.root_cost) return launch_ds<TT, D, 2>(p, blocks, stream);

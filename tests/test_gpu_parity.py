@@ -128,6 +128,38 @@ def test_medium_graph_leaf_parents(kmax):
         assert np.array_equal(api.count(g, tm), want_m), delta
 
 
+def test_epochs_hand_on_leftovers_exactly():
+    # an epoch ends as soon as a few waves are idle: the busy waves write what
+    # is left of their root-level windows as contexts, and later launches
+    # search them; no candidate is searched twice or skipped
+    s, d, t, n, ms = _medium(seed=3)
+    og = OracleGraph(s, d, t, n)
+    g = api.Graph(s, d, t, n)
+    carried = 0
+    for kmax in (3, 5):
+        mm = [m for m in ms if len(m) <= kmax]
+        for delta in (60, 200):
+            want = oracle_counts(og, mm, delta)
+            tr = api.Tree(mm, delta)
+            for pct, epochs, blocks, chunk in ((1, 16, 0, 64), (1, 3, 0, 64), (1, 2, 4, 128),
+                                               (50, 16, 2, 64), (100, 4, 1, 64)):
+                say("epochs", kmax, delta, pct, epochs, blocks)
+                log = np.zeros(epochs, np.int64)
+                got = api.count(g, tr, epoch_idle=pct, max_epochs=epochs, epoch_contexts=log,
+                                blocks=blocks, chunk=chunk)
+                assert np.array_equal(got, want), (kmax, delta, pct, epochs, blocks, log)
+                assert log[-1] == 0
+                carried += int(log.sum())
+            tm = api.Tree(mm, [7, delta, 3 * delta])
+            want_m = np.stack([oracle_counts(og, mm, x) for x in (7, delta, 3 * delta)])
+            assert np.array_equal(api.count(g, tm, epoch_idle=1), want_m), delta
+    assert carried > 0   # some epochs did end early and hand work on
+    with pytest.raises(api.MayuraError):
+        api.count(g, tr, epoch_idle=5, stats=True)
+    with pytest.raises(api.MayuraError):
+        api.count(g, tr, epoch_idle=101)
+
+
 @pytest.mark.parametrize("seed", range(3))
 def test_multi_window_tiny(seed):
     """One search for several windows equals the oracle at every window, on
