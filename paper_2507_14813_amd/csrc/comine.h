@@ -97,13 +97,19 @@ struct DevGraph {
 
 // A piece of search left over when an epoch ends: the candidates of one
 // root-level window, entries [e0, e1) of the list of group g of the root
-// a -> b at time t_lo | t_hi << 32.  The root itself was credited when it was
+// a -> b at time t_lo | t_hi << 32, with the root's windows in out(a), in(a),
+// out(b), in(b) as far as it had found them (first entry and length, as the
+// per-wave root windows keep them).  The root itself was credited when it was
 // started.
 struct EpochCtx {
     int32_t a, b;
     uint32_t t_lo, t_hi;
     uint32_t g, e0, e1, pad;
+    uint32_t hlo[4];
+    uint16_t hlen[4];
+    uint32_t pad2[2];
 };
+static_assert(sizeof(EpochCtx) == 64, "context record");
 constexpr uint32_t kCtxPiece = 64;   // candidates per context at most
 
 template <typename TT>

@@ -470,7 +470,7 @@ void fill_params(mg::KParams<TT> &p, const mg_graph *g, const mg_tree *tr, const
 // busy waves had not reached yet come back as contexts, which the next launch
 // spreads over all of its waves.  The last of max_epochs launches runs to the
 // end.  Counts accumulate in p.counts; p.queues is cleared before each launch.
-constexpr uint64_t kCtxCap = 1u << 21;   // contexts one epoch can hand on
+constexpr uint64_t kCtxCap = 1u << 20;   // contexts one epoch can hand on (64 MB)
 
 template <typename TT>
 int epoch_search(mg::KParams<TT> p, const mg_count_opts &o, hipStream_t st) {

@@ -333,7 +333,9 @@ struct LevelChain<TT, D, R, D> {};
 //
 // Root windows: for each root of the level-1 batch, the windows it found in
 // out(a), in(a), out(b), in(b) (index anchor * 2 + direction): first entry and
-// length, kNoHint as length when not found yet or 65535 entries or longer.  A deeper partial match of that root reads a window of the same
+// length, kNoHint as length when not found yet, kLongHint with the window's
+// end (not its first entry) when it has 65534 entries or more.  A deeper
+// partial match of that root reads a window of the same
 // list with t_prev < t <= t_first + delta, t_prev > t_first: it starts inside
 // the root's window and ends where it ends, so a bisection over the root's
 // window replaces a bisection over the whole list and the search for the end.
@@ -353,6 +355,7 @@ static_assert(sizeof(WaveLds<uint32_t, 5, 0>) % 16 == 0, "per-wave LDS block siz
 static_assert(sizeof(WaveLds<uint64_t, 5, 1>) % 16 == 0, "per-wave LDS block size");
 
 constexpr uint16_t kNoHint = 0xffff;
+constexpr uint16_t kLongHint = 0xfffe;
 
 // A new root a -> b in level-1 slot `slot`: its root windows are not found
 // yet; their first-entry words hold where they start, the first entries
@@ -510,25 +513,28 @@ __device__ __forceinline__ void count_leaf_parent(const KParams<TT> &p,
             const Entry<TT> *adj = dir == kDirOut ? p.g.out_adj : p.g.in_adj;
             const TT *ta = times_of(adj);
             uint32_t b = 0, e = 0, l0;
-            bool hinted = false;
+            bool hinted = false, whole = true;   // whole: [b, e) is the anchor's list
             if constexpr (D > 2) {
                 if (anc < 2) {
+                    // a root vertex's list: the window ends where the root's does
                     const uint32_t k = anc * 2u + dir;
                     const uint32_t hl = W.hlen[k][r1];
                     hinted = hl != kNoHint;
+                    whole = !hinted || hl == kLongHint;
                     b = W.hlo[k][r1];
-                    e = b + hl;
+                    e = hl == kLongHint ? b : b + hl;
                 }
             }
-            if (!hinted) {
+            if (whole) {
                 // the anchor's vertex by masks: a select chain over ph[]
                 // would be turned into an indexed load from scratch memory
                 int32_t a = 0;
 #pragma unroll
                 for (int t = 0; t < S; ++t) a |= ph[t] & -(int32_t)(anc == (uint32_t)t);
                 const uint32_t *off = dir == kDirOut ? p.g.out_off : p.g.in_off;
+                const uint32_t end = e;
                 b = off[a];
-                e = off[a + 1];
+                e = hinted ? end : off[a + 1];
             }
             const uint32_t le = (hdr >> 13) & 3u;
             if (le) {
@@ -681,12 +687,14 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, k
     // epochs: root-level candidates are written out as contexts instead of
     // expanded once enough waves are idle (polled every 16 passes)
     bool dumping = false, room = true;
-    uint32_t polls = 0;
+    uint32_t polls = 0, used = 0;   // contexts this wave wrote (at most its share of ctx_cap)
 
     for (;;) {
         bool done = false;
         if constexpr (L == 1 && epochs_of(MODE)) {
-            if (p.ctx_out && room && !dumping && (++polls & 15u) == 0) {
+            // (a wave dumps in one batch at most: the later batches of its
+            // chunk search on)
+            if (p.ctx_out && room && !dumping && !st.dumped && (++polls & 15u) == 0) {
                 uint32_t v = 0;
                 if (lane == 0) v = __hip_atomic_load(p.idle, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 const uint32_t waves = gridDim.x * (uint32_t)kWavesPerBlock;
@@ -751,20 +759,24 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, k
                         } else {
                             ta = times_of(dir == kDirOut ? p.g.out_adj : p.g.in_adj);
                             sh = 1;
+                            bool whole = true;   // [b, e) is the anchor's whole list
                             if constexpr (L > 1 && D > 2) {
                                 if (anc < 2) {
                                     const uint32_t k = (uint32_t)anc * 2u + (uint32_t)dir;
                                     const uint32_t r1 = A.r1[lo];
                                     const uint32_t hl = W.hlen[k][r1];
                                     hinted = hl != kNoHint;
+                                    whole = !hinted || hl == kLongHint;
                                     b = W.hlo[k][r1];
-                                    e = b + hl;
+                                    e = hl == kLongHint ? b : b + hl;
                                 }
                             }
-                            if (!hinted) {
+                            if (whole) {
                                 const int32_t a = vtx((uint32_t)anc, lo);
                                 const uint32_t *off = dir == kDirOut ? p.g.out_off : p.g.in_off;
-                                b = off[a]; e = off[a + 1];
+                                const uint32_t end = e;
+                                b = off[a];
+                                e = hinted ? end : off[a + 1];
                             }
                             if constexpr (L == 1) {
                                 // the root edge's own entries: its windows start at
@@ -794,8 +806,11 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, k
                         if constexpr (L == 1 && D > 2) {
                             if (!all && anc < 2) {
                                 const uint32_t k = (uint32_t)anc * 2u + (uint32_t)dir;
-                                W.hlo[k][lo] = l0;
-                                W.hlen[k][lo] = len < kNoHint ? (uint16_t)len : kNoHint;
+                                // a long window keeps its end, the list's start
+                                // then bounds the deeper bisections
+                                const bool lng = len >= kLongHint;
+                                W.hlo[k][lo] = lng ? l0 + len : l0;
+                                W.hlen[k][lo] = lng ? kLongHint : (uint16_t)len;
                             }
                         }
                     }
@@ -897,23 +912,14 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, k
                 const uint32_t n = c_hi > c_lo ? (c_hi - c_lo + kCtxPiece - 1) / kCtxPiece : 0u;
                 const uint32_t incl = incl_scan32(n, lane);
                 const uint32_t tot = lane_value(incl, kWave - 1);
-                unsigned long long base = 0;
-                uint32_t fits = 1;
-                if (lane == 0) {
-                    // take tot slots, only if all of them fit
-                    unsigned long long old =
-                        __hip_atomic_load(p.ctx_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    for (;;) {
-                        if (old + tot > p.ctx_cap) { fits = 0; break; }
-                        if (__hip_atomic_compare_exchange_strong(p.ctx_count, &old, old + tot,
-                                                                 __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                                 __HIP_MEMORY_SCOPE_AGENT))
-                            break;
-                    }
-                    base = old;
-                }
-                base = lane0_u64(base);
-                if (lane_value(fits, 0)) {
+                // every wave may write its share of the buffer, so one atomic
+                // add takes the slots and the buffer never overflows
+                const uint64_t share = p.ctx_cap / ((uint64_t)gridDim.x * kWavesPerBlock);
+                if ((uint64_t)used + tot <= share) {
+                    unsigned long long base = 0;
+                    if (lane == 0 && tot) base = atomicAdd(p.ctx_count, (unsigned long long)tot);
+                    base = lane0_u64(base);
+                    used += tot;
                     if (n) {
                         const uint32_t ox = wrec.x & 255, og = wrec.x >> 8;
                         const uint64_t tf = (uint64_t)tfirst_of(ox);
@@ -924,6 +930,12 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, k
                         c.t_hi = (uint32_t)(tf >> 32);
                         c.g = og;
                         c.pad = 0;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            c.hlo[k] = D > 2 ? W.hlo[k][ox] : 0u;
+                            c.hlen[k] = D > 2 ? W.hlen[k][ox] : kNoHint;
+                        }
+                        c.pad2[0] = c.pad2[1] = 0;
                         const unsigned long long slot = base + (incl - n);
                         for (uint32_t k = 0; k < n; ++k) {
                             const uint32_t c0 = c_lo + k * kCtxPiece;
@@ -935,7 +947,7 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, k
                     }
                     cc = T;
                 } else {
-                    dumping = false;   // no room left: this wave searches on
+                    dumping = false;   // its share is used up: this wave searches on
                     room = false;
                 }
             }
@@ -1149,8 +1161,7 @@ __device__ __forceinline__ void process_roots(const KParams<TT> &p,
 }
 
 // Search contexts [base, end) of p.ctx_in (at most 64): each becomes a
-// root in the level-1 batch, with its window given (its hints stay unknown:
-// deeper windows of the root's vertices are searched in the whole list).
+// root in the level-1 batch, with its window and its root windows given.
 template <typename TT, int D, int MODE>
 __device__ __forceinline__ void process_contexts(const KParams<TT> &p,
                                                  WaveLds<TT, D, keep_of(MODE)> &W,
@@ -1167,8 +1178,8 @@ __device__ __forceinline__ void process_contexts(const KParams<TT> &p,
             A.tfirst[lane] = (TT)(((uint64_t)c.t_hi << 32) | c.t_lo);
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                W.hlo[k][lane] = 0;
-                W.hlen[k][lane] = kNoHint;
+                W.hlo[k][lane] = c.hlo[k];
+                W.hlen[k][lane] = c.hlen[k];
             }
         }
         wave_sync();
@@ -1230,15 +1241,18 @@ comine_kernel(const KParams<TT> p) {
     bool from_ctx = false;
     if constexpr (epochs_of(MODE)) {
         if (p.ctx_in) {
-            // a later epoch: the contexts the last one left, 64 at a time
+            // a later epoch: the contexts the last one left, spread over every
+            // wave (up to 64 at a time)
             from_ctx = true;
+            const uint32_t waves = gridDim.x * (uint32_t)kWavesPerBlock;
+            const uint32_t per = min((uint32_t)kWave, max(1u, (p.n_ctx_in + waves - 1) / waves));
             for (;;) {
                 unsigned long long it = 0;
-                if (lane == 0) it = atomicAdd(&p.queues[kItemSlot * kQueueStride], (unsigned long long)kWave);
+                if (lane == 0) it = atomicAdd(&p.queues[kItemSlot * kQueueStride], (unsigned long long)per);
                 it = lane0_u64(it);
                 if (it >= p.n_ctx_in) break;
                 const uint32_t b0 = uniform((uint32_t)it);
-                process_contexts<TT, D, MODE>(p, W, cnt, lane, b0, min(b0 + (uint32_t)kWave, p.n_ctx_in), st);
+                process_contexts<TT, D, MODE>(p, W, cnt, lane, b0, min(b0 + per, p.n_ctx_in), st);
                 if (st.dumped) break;
             }
         }

@@ -162,6 +162,47 @@ def test_windows_past_the_chunk_limit():
     assert np.array_equal(got, want)
 
 
+def test_hub_root_windows_longer_than_16_bits():
+    """A hub with 70,000 out-edges in one window: the root windows of its
+    early edges in out(hub) have more than 65,533 entries, so deeper windows
+    on that list keep only the root window's end (and search their start from
+    the list's start).  Two- and three-edge motifs that reach out(hub) again
+    below the root, in co-mining, per-motif and leaf-parent paths, one and
+    two windows, against the oracle on the hub's first roots."""
+    rng = np.random.default_rng(31)
+    V, n_hub, n_rest = 1001, 70_000, 3_000
+    hs = np.zeros(n_hub, np.int32)
+    hd = rng.integers(1, V, n_hub).astype(np.int32)
+    ht = np.arange(1, n_hub + 1, dtype=np.int64)
+    rs = rng.integers(1, V, n_rest).astype(np.int32)
+    rd = ((rs + rng.integers(1, V - 1, n_rest)) % (V - 1) + 1).astype(np.int32)
+    rt = rng.integers(0, n_hub + 1, n_rest).astype(np.int64)
+    s, d, t = np.concatenate([hs, rs]), np.concatenate([hd, rd]), np.concatenate([ht, rt])
+    o = np.argsort(t, kind="stable")
+    s, d, t = s[o], d[o], t[o]
+    roots = np.flatnonzero(s == 0)[:6]
+    roots = np.concatenate([roots, rng.choice(len(s), 6, replace=False)])
+    ms = [[(0, 1), (0, 2), (2, 3)],      # sets the root's out(a) window (> 65,533 entries)
+          [(0, 1), (1, 2), (0, 3)],      # reads out(a) again below the root
+          [(0, 1), (1, 2), (0, 2)],
+          [(0, 1), (2, 1), (0, 3)],
+          [(0, 1), (1, 2)]]
+    delta = 100_000
+    g = api.Graph(s, d, t, V, sorted_by_t=True)
+    og = OracleGraph(s, d, t, V)
+    say("long hints: oracle")
+    want = oracle_counts(og, ms, delta, roots)
+    want2 = np.stack([oracle_counts(og, ms, 30_000, roots), want])
+    og.close()
+    assert want[1] > 0
+    for mode in ("comine", "per_motif"):
+        for ls in (0, 1):
+            say("long hints:", mode, ls)
+            got = api.count(g, api.Tree(ms, delta), roots=roots, mode=mode, leaf_scan=ls)
+            assert np.array_equal(got, want), (mode, ls)
+    assert np.array_equal(api.count(g, api.Tree(ms, [30_000, delta]), roots=roots), want2)
+
+
 def test_exit_with_live_handles():
     """A process that leaves graphs, trees, a batch and a model open and exits
     ends cleanly (handles still alive at exit are left to the process end)."""
