@@ -155,6 +155,25 @@ def idle_tail(api, g, tr, **kw):
             "start_spread_frac": float(st.max() - st.min()) / span}
 
 
+def epoch_runs(api, g, tr, ref, steps, warmup, pcts=(10, 25, 50)):
+    """Epochs (the paper's inter-warp load balancing): for each idle limit
+    (percent of the waves), the time per count and the contexts each launch
+    handed on; counts checked against the plain search."""
+    import numpy as np
+    out = {}
+    for pct in pcts:
+        def run():
+            return api.count(g, tr, epoch_idle=pct)
+        t, c = timed_steps(run, steps, warmup)
+        if not np.array_equal(c, ref):
+            raise SystemExit("epoch counts (idle limit %d %%) differ from the plain search" % pct)
+        carried = np.zeros(16, np.int64)
+        api.count(g, tr, epoch_idle=pct, epoch_contexts=carried)
+        out["idle_%d_pct" % pct] = {"ms": 1e3 * t,
+                                     "contexts": [int(x) for x in carried[:int(np.count_nonzero(carried)) + 1]]}
+    return out
+
+
 def timed_steps(fn, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -284,6 +303,9 @@ def bench_learned(args):
     assert np.array_equal(c, ref)
     balance = {"plain": idle_tail(api, g, tr), "learned": idle_tail(api, g, tr, model=model)}
     log("wave balance", balance)
+    epochs = epoch_runs(api, g, tr, ref, args.steps, args.warmup) if args.epochs else None
+    if epochs:
+        log("epochs", epochs)
     out = {
         "metric": "root edges searched/s, learned schedule (config 4), exact counts",
         "value": E / tl_, "unit": "root edges/s", "n_gpus": 1, "steps": args.steps,
@@ -293,6 +315,7 @@ def bench_learned(args):
         "config": {"workload": "powerlaw V=%d E=%d gamma=1.8 delta=%d, 756 motifs "
                                "(3- and 4-edge, <=4 nodes)" % (n, E, delta)},
         "plain_ms": 1e3 * tp_, "speedup_vs_plain": tp_ / tl_, "wave_balance": balance,
+        "epochs": epochs,
         "held_out_spearman": rho, "train_loss": [float(x) for x in loss], "train_s": train_s,
     }
     if args.per_motif_steps:
@@ -397,6 +420,8 @@ def main():
     ap.add_argument("--queues", type=int, default=0, help="root queues (0 = one per XCD)")
     ap.add_argument("--chunk", type=int, default=0, help="roots per queue grab (0 = default)")
     ap.add_argument("--no-tune", action="store_true", help="default launch settings, no autotuner")
+    ap.add_argument("--no-epochs", dest="epochs", action="store_false",
+                    help="skip the epoch (context offload) comparison")
     ap.add_argument("--config", type=int, default=2, choices=(2, 3, 4, 5),
                     help="2: the headline single-graph benchmark (default); 3: batched; "
                          "4: learned schedule; 5: learned + batched delta sweep")
@@ -496,6 +521,9 @@ def main():
 
     balance = idle_tail(api, g, tr, **kw)
     log("wave balance", balance)
+    epochs = epoch_runs(api, g, tr, counts, args.steps, args.warmup) if args.epochs else None
+    if epochs:
+        log("epochs", epochs)
     k_avg_s = sum(kms) / len(kms) / 1e3
     achieved = algo_bytes / k_avg_s / 1e9
     rec = counter_record(E)
@@ -553,6 +581,7 @@ def main():
         "stats": st,
         "tuning": tuning,
         "wave_balance": balance,
+        "epochs": epochs,
         "total_matches": int(counts.sum()),
     }
     if not args.no_cpu_baseline:
