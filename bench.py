@@ -298,7 +298,11 @@ def bench_learned(args):
     pred = model.predict(fe[lv])
     rank = lambda x: np.argsort(np.argsort(x))
     rho = float(np.corrcoef(rank(pred), rank(np.log1p(cost[lv])))[0, 1])
-    tp_, _ = timed_steps(lambda: api.count(g, tr), args.steps, args.warmup)
+    tuning = None if args.no_tune else api.tune(g, tr)
+    if tuning:
+        log("tuned", tuning)
+    kw = {k: tuning[k] for k in ("blocks", "chunk", "queues", "leaf_scan")} if tuning else {}
+    tp_, _ = timed_steps(lambda: api.count(g, tr, **kw), args.steps, args.warmup)
     tl_, c = timed_steps(lambda: api.count(g, tr, model=model), args.steps, args.warmup)
     assert np.array_equal(c, ref)
     balance = {"plain": idle_tail(api, g, tr), "learned": idle_tail(api, g, tr, model=model)}
@@ -315,7 +319,7 @@ def bench_learned(args):
         "config": {"workload": "powerlaw V=%d E=%d gamma=1.8 delta=%d, 756 motifs "
                                "(3- and 4-edge, <=4 nodes)" % (n, E, delta)},
         "plain_ms": 1e3 * tp_, "speedup_vs_plain": tp_ / tl_, "wave_balance": balance,
-        "epochs": epochs,
+        "epochs": epochs, "tuning": tuning,
         "held_out_spearman": rho, "train_loss": [float(x) for x in loss], "train_s": train_s,
     }
     if args.per_motif_steps:
@@ -364,7 +368,11 @@ def bench_sweep(args):
     del s, d, t
     t3, out = timed_steps(lambda: [api.count(g, tr) for tr in trees], args.steps, args.warmup)
     assert np.array_equal(np.stack(out), ref)
-    t1, out = timed_steps(lambda: api.count(g, tm), args.steps, args.warmup)
+    tuning = None if args.no_tune else api.tune(g, tm)
+    if tuning:
+        log("tuned", tuning)
+    kw = {k: tuning[k] for k in ("blocks", "chunk", "queues", "leaf_scan")} if tuning else {}
+    t1, out = timed_steps(lambda: api.count(g, tm, **kw), args.steps, args.warmup)
     assert np.array_equal(out, ref)
     balance = idle_tail(api, g, tm)
     log("wave balance", balance)
@@ -394,6 +402,7 @@ def bench_sweep(args):
         "config": {"workload": "powerlaw V=%d E=%d gamma=2.0 span=1e8 s, 48 motifs of 3-5 "
                                "edges, windows %s" % (n, E, windows)},
         "three_searches_ms": 1e3 * t3, "speedup_vs_three_searches": t3 / t1,
+        "tuning": tuning,
         "wave_balance": balance,
         "learned_batched_ms": 1e3 * (tl + predict_s), "learned_batched_step_ms": 1e3 * tl,
         "learned_predict_ms": 1e3 * predict_s, "speedup_learned_vs_plain": t1 / (tl + predict_s),
