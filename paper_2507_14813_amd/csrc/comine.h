@@ -149,14 +149,16 @@ struct KParams {
     unsigned long long *wave_clock;  // NULL, or per wave: start and end of its search
                                      // (device real-time clock ticks)
     uint32_t n_wave_clock;           // waves that wave_clock holds
-    // epochs (MODE 0 and 3): ctx_out NULL = off.  A wave that finds no work
+    // epochs (the kernels' MODE 5 and 6, MODE 0 and 3 with epochs): ctx_out
+    // and ctx_in NULL = off.  A wave that finds no work
     // left adds one to *idle; once *idle reaches idle_pct percent of the
     // launch's waves, the waves still searching stop expanding root-level
     // candidates, write what is left of their root-level windows as contexts,
     // finish what they already hold and exit.  The next launch searches the
     // contexts (ctx_in) instead of the root queues, claiming them through the
     // item slot of `queues`.
-    EpochCtx *ctx_out;            // contexts written (ctx_cap at most)
+    EpochCtx *ctx_out;            // contexts written (ctx_cap at most; each wave at
+                                  // most its share, ctx_cap / waves)
     unsigned long long *ctx_count;  // contexts written so far (zeroed)
     unsigned long long ctx_cap;
     uint32_t *idle;               // idle waves (zeroed)
