@@ -114,3 +114,40 @@ def test_multi_window_trees():
     api.Tree(big, [1, 2, 3, 4, 5])                      # 3,780 counters
     with pytest.raises(api.MayuraError, match="MG_EUNSUPPORTED"):
         api.Tree(big, [1, 2, 3, 4, 5, 6])               # 4,536 > 4,096 counters
+
+
+# C struct of the header -> its ctypes mirror in the binding
+_MIRRORS = [("mg_graph_info_t", "GraphInfo"), ("mg_tree_info_t", "TreeInfo"),
+            ("mg_count_opts", "CountOpts"), ("mg_tune_result", "TuneResult"),
+            ("mg_cpu_opts", "CpuOpts"), ("mg_advice", "Advice"), ("mg_cursor", "Cursor"),
+            ("mg_batch_opts", "BatchOpts"), ("mg_batch_info_t", "BatchInfo")]
+
+
+def test_ctypes_mirrors_match_the_header(tmp_path):
+    """Every structure the binding passes through the C ABI has the size and
+    field offsets the header gives it (compiled with the host C compiler)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "mayura.h"', "int main(void) {"]
+    for cname, pyname in _MIRRORS:
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in getattr(api, pyname)._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        c, f, v = line.split()
+        got[(c, f)] = int(v)
+    for cname, pyname in _MIRRORS:
+        cls = getattr(api, pyname)
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
