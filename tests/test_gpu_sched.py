@@ -210,6 +210,17 @@ def test_learned_schedule_counts_are_exact():
         live = cost > 0
         m.train(f[live], np.log1p(cost[live]).astype(np.float32), epochs=3, lr=2e-3)
         assert np.array_equal(api.count(g, tr, model=m), want)
+        # adversarial predictions: the trained costs in reverse order (the output
+        # layer negated), and one huge cost for every root
+        w = m.weights()
+        inv = w.copy()
+        inv[-(64 + 1):] *= -1.0
+        flat = w.copy()
+        flat[-(64 + 1):-1] = 0.0
+        flat[-1] = 30.0
+        for bad in (inv, flat):
+            say("adversarial model", delta)
+            assert np.array_equal(api.count(g, tr, model=api.Model(weights=bad)), want)
     wl = W.make_config(2, scale=0.01)
     s, d, t, n = wl.graphs[0]
     g = api.Graph(s, d, t, n)
