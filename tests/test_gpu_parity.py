@@ -128,6 +128,37 @@ def test_medium_graph_leaf_parents(kmax):
         assert np.array_equal(api.count(g, tm), want_m), delta
 
 
+def test_closing_edges_from_hub_out_lists():
+    # three-edge motifs whose last edge leaves the second-edge vertex x for a
+    # root vertex (x -> a, x -> b): a lane may count those edges in the root's
+    # in-lists instead of x's out-list, whichever is shorter.  Hubs with long
+    # out-lists or long in-lists make either choice happen, and the three
+    # windows put the in-list suffixes below and above 16 entries.
+    rng = np.random.default_rng(11)
+    n, e = 400, 24000
+    s = rng.integers(0, n, e)
+    d = rng.integers(0, n, e)
+    hub_out = rng.random(e) < 0.25
+    s[hub_out] = rng.integers(0, 3, hub_out.sum())
+    hub_in = rng.random(e) < 0.15
+    d[hub_in] = rng.integers(3, 5, hub_in.sum())
+    keep = s != d
+    s, d = s[keep].astype(np.int32), d[keep].astype(np.int32)
+    t = np.sort(rng.integers(0, 30000, len(s))).astype(np.int64)
+    ms = W.enumerate_motifs(3, 3, connected=False)
+    og = OracleGraph(s, d, t, n)
+    g = api.Graph(s, d, t, n)
+    for delta in (6, 60, 400, 1500):
+        want = oracle_counts(og, ms, delta)
+        assert want.sum() > 0
+        tr = api.Tree(ms, delta)
+        for ls in (0, 5, 256):
+            say("hub closing edges", delta, ls)
+            assert np.array_equal(api.count(g, tr, leaf_scan=ls), want), (delta, ls)
+        say("hub closing edges, epochs", delta)
+        assert np.array_equal(api.count(g, tr, epoch_idle=50), want), delta
+
+
 def test_epochs_hand_on_leftovers_exactly():
     # an epoch ends as soon as a few waves are idle: the busy waves write what
     # is left of their root-level windows as contexts, and later launches
