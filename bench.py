@@ -174,6 +174,20 @@ def epoch_runs(api, g, tr, ref, steps, warmup, pcts=(10, 25, 50)):
     return out
 
 
+def cost_distribution(cost):
+    """Per-root search cost from the instrumented kernel's cost log (equal to
+    the oracle's per-root window log in the GPU tests): window entries
+    examined below each searched root, their mean, median, 99th percentile
+    and maximum."""
+    import numpy as np
+    live = cost[cost > 0].astype(np.float64) - 1.0
+    if not len(live):
+        return None
+    return {"unit": "window entries per root", "roots": int(len(live)),
+            "mean": float(live.mean()), "p50": float(np.percentile(live, 50)),
+            "p99": float(np.percentile(live, 99)), "max": float(live.max())}
+
+
 def timed_steps(fn, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -321,6 +335,7 @@ def bench_learned(args):
         "plain_ms": 1e3 * tp_, "speedup_vs_plain": tp_ / tl_, "wave_balance": balance,
         "epochs": epochs, "tuning": tuning,
         "held_out_spearman": rho, "train_loss": [float(x) for x in loss], "train_s": train_s,
+        "root_cost": cost_distribution(cost),
     }
     if args.per_motif_steps:
         tpm, c = timed_steps(lambda: api.count(g, tr, mode="per_motif"), 1, 1)
@@ -408,6 +423,7 @@ def bench_sweep(args):
         "learned_predict_ms": 1e3 * predict_s, "speedup_learned_vs_plain": t1 / (tl + predict_s),
         "train_loss": [float(x) for x in loss], "counts_total": [int(r.sum()) for r in ref],
         "oracle_sampled_roots": int(len(roots)), "oracle_s": oracle_s,
+        "root_cost": cost_distribution(cost),
     }
     if args.per_motif_steps:
         tpm, out = timed_steps(lambda: api.count(g, tm, mode="per_motif"), 1, 1)
@@ -530,6 +546,8 @@ def main():
 
     balance = idle_tail(api, g, tr, **kw)
     log("wave balance", balance)
+    root_cost = cost_distribution(api.count(g, tr, root_cost=True)[1])
+    log("root cost", root_cost)
     epochs = epoch_runs(api, g, tr, counts, args.steps, args.warmup) if args.epochs else None
     if epochs:
         log("epochs", epochs)
@@ -590,6 +608,7 @@ def main():
         "stats": st,
         "tuning": tuning,
         "wave_balance": balance,
+        "root_cost": root_cost,
         "epochs": epochs,
         "total_matches": int(counts.sum()),
     }
