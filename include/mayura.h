@@ -168,7 +168,11 @@ typedef struct {
                                  own lane when at most this long, by the whole
                                  wave (one ballot per bound vertex) when longer.
                                  0 = default (256), < 0 = never (every window goes
-                                 through the candidate expansion) */
+                                 through the candidate expansion).  In trees of
+                                 three edges, a window on a later vertex's out-list
+                                 whose edges can only close on the root's vertices
+                                 may instead be counted, by its lane, in those
+                                 vertices' in-lists when they are shorter. */
     const struct mg_model *model;   /* cost model for MG_SCHED_LEARNED */
     uint64_t *root_cost;      /* optional out, n_edges entries indexed by root edge:
                                  1 + the candidate edges examined (window entries)
