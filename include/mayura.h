@@ -465,7 +465,9 @@ typedef struct {
     int32_t item_roots;       /* chosen (or given) item size */
     int32_t blocks;           /* 0 = filled the device */
     int32_t graph_captured;   /* 1 once a HIP graph replays the step */
-    int32_t depth;            /* deepest tree */
+    int32_t depth;            /* depth of the search kernel: the deepest tree's
+                                 edges, or 4 for a three-edge tree with a two-edge
+                                 prefix on four vertices */
     float tuned_ms;           /* best step time seen by the autotuner (0 if none) */
     int32_t learned;          /* 1 when items come from the cost model */
     float predict_ms;         /* wall time of the cost model at creation: features,

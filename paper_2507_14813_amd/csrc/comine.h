@@ -67,6 +67,9 @@ struct DevTree {
     int32_t n_q;        // distinct motifs
     int32_t root_q;     // query id of the one-edge prefix, -1 if none
     int32_t depth;      // longest motif in edges
+    int32_t kdepth;     // kernel instantiation that searches it: depth, or 4
+                        // for a depth-3 tree with a buffered two-edge prefix
+                        // on four vertices (depth-3 kernels keep three)
     int32_t n_d;        // windows (1..kMaxDeltas), counter slots per motif
 };
 __host__ __device__ inline int32_t counter_slots(const DevTree &t) { return t.n_q * t.n_d; }

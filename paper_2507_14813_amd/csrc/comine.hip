@@ -76,7 +76,7 @@ hipError_t launch_fill_u64(unsigned long long *p, uint32_t n, unsigned long long
 
 template <typename TT>
 hipError_t launch_comine(const KParams<TT> &p, int blocks, hipStream_t stream) {
-    switch (p.tree.depth) {
+    switch (p.tree.kdepth) {
         case 1: return launch_d<TT, 1>(p, blocks, stream);
         case 2: return launch_d<TT, 2>(p, blocks, stream);
         case 3: return launch_d<TT, 3>(p, blocks, stream);

@@ -77,6 +77,7 @@ struct mg_tree {
     std::vector<int32_t> node_tab;      // one word per internal node
     std::vector<int32_t> grp_tab;       // 8 words per group
     int32_t depth = 0, root_q = -1;
+    int32_t kdepth = 0;    // depth of the kernel that searches it (DevTree::kdepth)
     mg_tree_info_t info{};
     // device copies
     int device = -1;

@@ -269,9 +269,11 @@ int build_tree(mg_tree *tr) {
     tr->node_tab.assign(n_int > 0 ? n_int : 1, 0);
     tr->grp_tab.clear();
     tr->depth = 0;
+    bool wide2 = false;   // an internal two-edge prefix on four vertices
     for (int n = 0; n < N; ++n) {
         const TrieNode &nd = tr->nodes[n];
         tr->depth = std::max(tr->depth, nd.depth);
+        if (nd.depth == 2 && nd.nv > 3 && !nd.kids.empty()) wide2 = true;
         if (nd.kids.empty()) continue;
         // group the children by the list they scan
         std::map<std::pair<int, int>, std::vector<int>> groups;
@@ -332,6 +334,7 @@ int build_tree(mg_tree *tr) {
     }
     if (tr->grp_tab.empty()) tr->grp_tab.assign(8, 0);
     tr->root_q = tr->nodes[0].q;
+    tr->kdepth = (tr->depth == 3 && wide2) ? 4 : tr->depth;
 
     // MG-Tree view: the root is the longest prefix shared by every motif;
     // below it a node exists where a prefix is a query or branches.
@@ -633,6 +636,7 @@ mg::DevTree dev_tree(const mg_tree *tr) {
     t.n_q = (int32_t)tr->distinct.size();
     t.root_q = tr->root_q;
     t.depth = tr->depth;
+    t.kdepth = tr->kdepth;
     t.n_d = (int32_t)tr->deltas.size();
     return t;
 }
@@ -1153,7 +1157,7 @@ int mg_batch_create(const mg_graph *const *graphs, const mg_tree *const *trees, 
             b->total_motifs += tr->n_motifs * (int32_t)tr->delta_slot.size();
             b->total_roots += graphs[j]->E;
             b->n_q_max = std::max<uint32_t>(b->n_q_max, (uint32_t)n_slots(tr));
-            b->depth = std::max(b->depth, tr->depth);
+            b->depth = std::max(b->depth, tr->kdepth);
         }
         b->time_bytes = graphs[0]->time_bytes;
         int rc = b->time_bytes == 4 ? upload_jobs<uint32_t>(b.get(), st)

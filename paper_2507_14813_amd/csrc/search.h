@@ -294,10 +294,11 @@ __device__ __forceinline__ uint32_t leaf_scan_wave_multi(const KParams<TT> &p,
 // R: 1 = each partial match also keeps its root edge (the per-root cost log),
 // 2 = its root edge and the slot of its parent one level up (enumeration,
 // which writes out every matched edge).
-template <typename TT, int L, int R>
+// V: vertex slots, the most motif vertices bound at this level (vslots).
+template <typename TT, int L, int R, int V>
 struct LevelBuf {
-    static constexpr int S = (2 * L < kVMax) ? 2 * L : kVMax;   // vertex slots
-    static constexpr int C = 2 * kWave;                          // capacity
+    static constexpr int S = V;              // vertex slots
+    static constexpr int C = 2 * kWave;      // capacity
     // phi[s - 2][i]: graph vertex of motif vertex s >= 2; motif vertices 0 and
     // 1 and t_first are the root's, kept once in the level-1 batch (slot r1)
     int32_t phi[S - 2][C];
@@ -309,8 +310,8 @@ struct LevelBuf {
     uint32_t root[R ? C : 1];
     uint8_t par[R == 2 && L > 2 ? C : 1];   // slot of its parent at level L - 1
 };
-template <typename TT, int R>
-struct LevelBuf<TT, 1, R> {
+template <typename TT, int R, int V>
+struct LevelBuf<TT, 1, R, V> {
     static constexpr int S = 2;
     static constexpr int C = kWave;
     int32_t phi[2][kWave];
@@ -318,9 +319,18 @@ struct LevelBuf<TT, 1, R> {
     uint32_t root[R ? kWave : 1];
 };
 
+// Vertex slots at level L of a kernel for trees of depth D: two per edge, at
+// most kVMax.  Depth-3 kernels keep three at level 2, which holds for trees
+// whose buffered two-edge prefixes share a vertex; the host runs trees with a
+// four-vertex two-edge prefix on the depth-4 kernel (DevTree::kdepth).  The
+// slot saved is registers the compiler no longer spills.
+constexpr int vslots(int D, int L) {
+    return (D == 3 && L == 2) ? 3 : (2 * L < kVMax ? 2 * L : kVMax);
+}
+
 template <typename TT, int D, int R, int L>
 struct LevelChain {
-    LevelBuf<TT, L, R> buf;
+    LevelBuf<TT, L, R, vslots(D, L)> buf;
     LevelChain<TT, D, R, L + 1> next;
 };
 template <typename TT, int D, int R>
@@ -371,7 +381,7 @@ __device__ __forceinline__ void set_root_slot(WaveLds<TT, D, R> &W, uint32_t slo
 }
 
 template <int L, typename TT, int D, int R, int M>
-__device__ __forceinline__ LevelBuf<TT, L, R> &lvl(LevelChain<TT, D, R, M> &c) {
+__device__ __forceinline__ LevelBuf<TT, L, R, vslots(D, L)> &lvl(LevelChain<TT, D, R, M> &c) {
     if constexpr (L == M) return c.buf;
     else return lvl<L>(c.next);
 }
@@ -391,7 +401,7 @@ __device__ __forceinline__ void edge_chain(WaveLds<TT, D, 2> &W, uint32_t i, uin
     if constexpr (L == 1) {
         e[0] = lvl<1>(W.lv).root[i];
     } else {
-        LevelBuf<TT, L, 2> &A = lvl<L>(W.lv);
+        auto &A = lvl<L>(W.lv);
         e[L - 1] = A.eid[i];
         if constexpr (L == 2) edge_chain<1>(W, A.r1[i], e);
         else edge_chain<L - 1>(W, A.par[i], e);
@@ -649,9 +659,9 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, k
                                           const uint32_t nparts = 1,
                                           const EpochCtx *ctx = nullptr) {
     constexpr bool STATS = MODE == 1, LOG = MODE == 2;
-    LevelBuf<TT, L, keep_of(MODE)> &A = lvl<L>(W.lv);
-    constexpr int SA = LevelBuf<TT, L, keep_of(MODE)>::S;
-    LevelBuf<TT, 1, keep_of(MODE)> &R1 = lvl<1>(W.lv);
+    auto &A = lvl<L>(W.lv);
+    constexpr int SA = vslots(D, L);
+    auto &R1 = lvl<1>(W.lv);
     // graph vertex of motif vertex s, and t_first, of buffered partial match i
     auto vtx = [&](uint32_t s, uint32_t i) -> int32_t {
         if constexpr (L == 1) return A.phi[s][i];
@@ -1090,8 +1100,8 @@ __device__ __forceinline__ void run_level(const KParams<TT> &p, WaveLds<TT, D, k
                 write_matches(p, valid && cw && q1, q1 - 1u, e, L + 1);
             }
             if constexpr (L + 1 < D) {
-                LevelBuf<TT, L + 1, keep_of(MODE)> &B = lvl<L + 1>(W.lv);
-                constexpr int SB = LevelBuf<TT, L + 1, keep_of(MODE)>::S;
+                auto &B = lvl<L + 1>(W.lv);
+                constexpr int SB = vslots(D, L + 1);
                 const bool push = (cw >> 31) != 0;
                 const uint64_t pm = __ballot(push);
                 if (push) {
@@ -1149,7 +1159,7 @@ __device__ __forceinline__ void process_root_part(const KParams<TT> &p,
         }
     }
     if constexpr (D > 1) {
-        LevelBuf<TT, 1, keep_of(MODE)> &A = lvl<1>(W.lv);
+        auto &A = lvl<1>(W.lv);
         if (lane == 0) {
             A.phi[0][0] = s;
             A.phi[1][0] = d;
@@ -1197,7 +1207,7 @@ __device__ __forceinline__ void process_roots(const KParams<TT> &p,
             if (ok) atomicAdd(&p.root_cost[r], 1ull);
         }
         if constexpr (D > 1) {
-            LevelBuf<TT, 1, keep_of(MODE)> &A = lvl<1>(W.lv);
+            auto &A = lvl<1>(W.lv);
             if (ok) {
                 const uint32_t slot = mbcnt(m);
                 A.phi[0][slot] = s;
@@ -1225,7 +1235,7 @@ __device__ __forceinline__ void process_contexts(const KParams<TT> &p,
                                                  const uint32_t base, const uint32_t end,
                                                  Stats &st) {
     if constexpr (D > 1) {
-        LevelBuf<TT, 1, keep_of(MODE)> &A = lvl<1>(W.lv);
+        auto &A = lvl<1>(W.lv);
         const uint32_t i = base + (uint32_t)lane;
         if (i < end) {
             const EpochCtx c = p.ctx_in[i];

@@ -159,6 +159,35 @@ def test_closing_edges_from_hub_out_lists():
         assert np.array_equal(api.count(g, tr, epoch_idle=50), want), delta
 
 
+def test_three_edge_trees_with_a_four_vertex_prefix():
+    # depth-3 kernels keep three vertices per level-2 partial match; a tree
+    # whose two-edge prefix spans four vertices (and goes deeper) runs on the
+    # depth-4 kernel, in every mode and in batches
+    s, d, t, n, _ = _medium(seed=3)
+    og = OracleGraph(s, d, t, n)
+    g = api.Graph(s, d, t, n)
+    conn = W.enumerate_motifs(3, 3)
+    wide = [m for m in W.enumerate_motifs(3, 4, connected=False)
+            if len({v for e in m[:2] for v in e}) == 4][:12]
+    assert wide
+    for ms, kdepth in ((conn, 3), (conn + wide, 4)):
+        for delta in (7, 40):
+            say("four-vertex prefix", kdepth, delta)
+            want = oracle_counts(og, ms, delta)
+            tr = api.Tree(ms, delta)
+            assert np.array_equal(api.count(g, tr), want), (kdepth, delta)
+            assert np.array_equal(api.count(g, tr, mode="per_motif"), want)
+            c, st = api.count(g, tr, stats=True)
+            assert np.array_equal(c, want)
+            assert np.array_equal(api.count(g, tr, epoch_idle=50), want)
+            tm = api.Tree(ms, [3, delta])
+            want_m = np.stack([oracle_counts(og, ms, 3), want])
+            assert np.array_equal(api.count(g, tm), want_m)
+            b = api.Batch([g], [tr], item_roots=64)
+            assert b.info()["depth"] == kdepth
+            assert np.array_equal(b.count()[0], want)
+
+
 def test_epochs_hand_on_leftovers_exactly():
     # an epoch ends as soon as a few waves are idle: the busy waves write what
     # is left of their root-level windows as contexts, and later launches
