@@ -537,11 +537,18 @@ int launch_tree(const mg_graph *g, mg_tree *tr, const uint32_t *d_roots, uint32_
         for (int i = 0; i < mg::kQueues; ++i) q[(size_t)i * mg::kQueueStride] = o.cursor->head[i];
         HIP_TRY(hipMemcpyAsync(d_queues, q.data(), kQueueBytes, hipMemcpyHostToDevice, st));
         HIP_TRY(hipStreamSynchronize(st));   // q is released on return
+    }
+    const uint32_t n_counts = (uint32_t)mg::counter_slots(p.tree);
+    if (!(o.cursor && o.cursor->started) && d_counts == d_queues + mg::kQueueWords) {
+        // queue heads and counters side by side: one fill kernel clears both
+        // (cheaper on the host than two memsets, and no memset node when the
+        // caller captures the stream)
+        HIP_TRY(mg::launch_fill_u64(d_queues, (uint32_t)mg::kQueueWords + n_counts, 0ull, st));
     } else {
-        HIP_TRY(hipMemsetAsync(d_queues, 0, kQueueBytes, st));
+        if (!(o.cursor && o.cursor->started)) HIP_TRY(hipMemsetAsync(d_queues, 0, kQueueBytes, st));
+        HIP_TRY(hipMemsetAsync(d_counts, 0, sizeof(unsigned long long) * n_counts, st));
     }
     if (d_stats) HIP_TRY(hipMemsetAsync(d_stats, 0, sizeof(unsigned long long) * mg::kStats, st));
-    HIP_TRY(hipMemsetAsync(d_counts, 0, sizeof(unsigned long long) * mg::counter_slots(p.tree), st));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (ms) {
         HIP_TRY(hipEventCreate(&e0));
